@@ -1,0 +1,206 @@
+"""Throughput benchmark of the MBS iteration on one MI355X.
+
+A step is one iteration of the modified Born series (Eq. 6 of the paper) over
+every subdomain of the workload: edge corrections, the five FFT passes with the
+fused pointwise work, the face update and the FP64 residual reduction.  The
+default workload is the 1024^3 grid decomposed 2x2x2 into 512^3 subdomains
+(planar source, 32-voxel absorbing ramps, t = 8), run for a fixed number of
+iterations with all inputs already resident in HBM.
+
+Prints one JSON line with whole-job voxel-updates/s, the roofline of the
+dominant kernel (HIP events around every launch of the timed region) and a
+bounded timing of the FP64 CPU oracle.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MBS voxel-updates/s + HBM GB/s at 1024³; served solves/s and p99 latency"
+
+
+def slab_elems(n, S, t, a, d):
+    plane = n[1] * n[2] if d == 0 else (n[0] * n[2] if d == 1 else n[0] * n[1])
+    return S * 2 * t * plane if a[d] else 0
+
+
+def face_voxels(n, t, a):
+    """Voxels per subdomain in the union of the t-deep edge slabs of corrected axes."""
+    inner = 1
+    for d in range(3):
+        inner *= (n[d] - 2 * t) if a[d] else n[d]
+    return n[0] * n[1] * n[2] - inner
+
+
+def algorithmic_bytes(shape, split, periodic, t, src_box):
+    """Compulsory HBM bytes per launch of each kernel kind for one slot."""
+    n = [shape[d] // split[d] for d in range(3)]
+    S = split[0] * split[1] * split[2]
+    a = [2 if split[d] >= 2 else (0 if periodic[d] else 1) for d in range(3)]
+    V = S * n[0] * n[1] * n[2]
+    slabs = sum(slab_elems(n, S, t, a, d) for d in range(3))
+    fv = S * face_voxels(n, t, a)
+    L = 2048 // n[2] if n[2] < 2048 else 1
+    n_main = (S * n[0] * n[1] + L - 1) // L
+    n_face = (fv + 255) // 256
+    return {
+        # read x, B (+ edge corrections, source box), write W
+        "first_z": 24 * V + 8 * slabs + 8 * src_box,
+        "mid_y_fwd": 16 * V,
+        "green_x": 16 * V,
+        "mid_y_inv": 16 * V,
+        # read W, x, B, write x (+ edge slabs of u, partial sums)
+        "last_z": 32 * V + 8 * slabs + 8 * n_main,
+        # per axis: read the slab values, write the corrections
+        "edge_corr": 16 * slabs,
+        # read corrections, u, B, x; write x and the iterate's edge slabs
+        "face": 8 * (2 * slabs + 4 * fv) + 8 * n_face,
+        "reduce": 8 * (n_main + n_face),
+    }
+
+
+def cpu_baseline(n_dev, S_dev, w, iters=3, edge=256):
+    """Time the FP64 oracle on a bounded sample: the first edge^3 block of the
+    workload's medium and source, decomposed like the workload."""
+    import numpy as np
+    from oracle import mbs_oracle as O
+    n = n_dev[:edge, :edge, :edge].cpu().numpy()
+    S = S_dev[:edge, :edge, :edge].cpu().numpy()
+    shape = (edge,) * 3
+    pr = O.MBSProblem(shape, w.split, w.periodic, w.t, n, w.k_vac, w.ramp_width, w.ramp_max, alpha=w.alpha)
+    y = pr.source_term(S)
+    x = np.zeros(shape, np.complex128)
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        x, _ = pr.step(x, y)
+    dt = time.perf_counter() - t0
+    return {
+        "value": edge ** 3 * iters / dt,
+        "unit": "voxel-updates/s",
+        "cores": O.WORKERS,
+        "kind": "oracle",
+        "sample": (f"{iters} iterations of the FP64 oracle on the first {edge}^3 block of the workload's "
+                   f"medium and source, split {w.split[0]}x{w.split[1]}x{w.split[2]} like the workload "
+                   f"(t={w.t}, ramp {w.ramp_width[0]}), {dt:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="dd1024")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: every subdomain of the workload is resident on a single "
+              f"MI355X; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from mbs_inputs import source_tensor, workload, workload_inputs
+    from paper_2410_02395_amd import mbs
+
+    w = workload(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print(f"[bench] workload {w.name} shape {w.shape} split {w.split}", file=sys.stderr, flush=True)
+    n, _ = (None, None)
+    if w.medium["kind"] == "random":
+        from mbs_inputs import smoothed_random_medium
+        n = smoothed_random_medium(w.shape, w.medium["seed"], w.medium["n_min"], w.medium["n_max"],
+                                   sigma=w.ppw / 2.0, device="cuda:0")
+    else:
+        n = torch.from_numpy(workload_inputs(w)[0]).to(dev)
+    S = source_tensor(w, "cuda:0")
+    nz = torch.nonzero(S.abs() > 0)
+    box = 1
+    for d in range(3):
+        box *= int(nz[:, d].max() - nz[:, d].min() + 1)
+    torch.cuda.synchronize()
+    plan = mbs.Plan(w.shape, w.split, w.periodic, w.t, 1, w.alpha, flags=mbs.MBS_TIMING,
+                    check_every=min(50, max(1, args.steps)))
+    plan.set_medium(0, n, w.k_vac, w.ramp_width, w.ramp_max)
+    out = torch.empty(w.shape, dtype=torch.complex64, device=dev)
+    print("[bench] medium set; warmup", file=sys.stderr, flush=True)
+    if args.warmup > 0:
+        plan.solve(0, S, 0.0, args.warmup, out=out)
+    plan.timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, res = plan.solve(0, S, 0.0, args.steps, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tim = plan.timing()
+    assert res["iterations"] == args.steps, res
+    print(f"[bench] timed {args.steps} iterations in {dt:.3f} s", file=sys.stderr, flush=True)
+
+    vox = w.voxels
+    value = vox * args.steps / dt
+    ab = algorithmic_bytes(w.shape, w.split, w.periodic, w.t, box)
+    kernels = {}
+    total_bytes_iter = 0
+    for k, (ms, cnt) in tim.items():
+        if cnt == 0:
+            continue
+        per_iter = cnt / args.steps
+        avg = ms / cnt
+        kernels[k] = {"avg_ms": avg, "launches": cnt, "bytes": ab[k],
+                      "gbps": ab[k] / (avg * 1e-3) / 1e9}
+        total_bytes_iter += ab[k] * per_iter
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    dk = kernels[dom]
+    achieved = dk["gbps"]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_ms": round(dk["avg_ms"], 4), "bytes_per_launch": dk["bytes"]}
+    hbm_gbps = total_bytes_iter * args.steps / dt / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(n, S, w)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{w.name}: {w.shape[0]}x{w.shape[1]}x{w.shape[2]} complex64 as "
+                         f"{w.split[0]}x{w.split[1]}x{w.split[2]} subdomains, t={w.t}, {w.ppw:g} ppw, "
+                         f"seeded smoothed random medium n in [{w.medium.get('n_min', 1)},"
+                         f"{w.medium.get('n_max', 1)}], {w.source['kind']} source, "
+                         f"{w.ramp_width[0]}-voxel absorbing ramps, fixed {args.steps} iterations"),
+            "voxels": vox,
+            "residual_reductions": "f64",
+        },
+        "hbm_gbps": round(hbm_gbps, 1),
+        "bytes_per_voxel_update": round(total_bytes_iter / vox, 2),
+        "rel_residual_after": res["rel_residual"],
+        "kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "gbps": round(v["gbps"], 1)} for k, v in kernels.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

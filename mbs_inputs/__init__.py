@@ -14,6 +14,7 @@ from .generators import (  # noqa: F401
     point_source,
     poisson_requests,
     smoothed_random_medium,
+    source_tensor,
     sphere_medium,
     workload,
     workload_inputs,

@@ -7,7 +7,9 @@ Conventions (shared by every consumer):
     per wavelength); the method turns it into ``k^2`` itself.
 
 Random media follow one recipe: white N(0,1) noise from a seeded
-``torch.Generator`` on the CPU, a periodic separable Gaussian filter of
+``torch.Generator`` on the device that will hold the medium (the CPU stream
+and the GPU stream of one seed differ; every comparison hands the same
+returned array to both sides), a periodic separable Gaussian filter of
 standard deviation ``sigma = ppw/2`` voxels (so the autocorrelation of the
 smoothed field is ``exp(-r^2/lambda^2)``, a one-wavelength correlation), then a
 min-max rescale to [0, 1] and ``n = n_min + (n_max - n_min) * u``.  The
@@ -60,9 +62,8 @@ def smoothed_random_medium(shape: Shape, seed: int, n_min: float, n_max: float,
     Returns a numpy complex64 array when ``device == "cpu"``, else a complex64
     torch tensor on ``device`` (large grids are generated where they are used).
     """
-    gen = torch.Generator(device="cpu").manual_seed(int(seed))
-    u = torch.randn(shape, generator=gen, dtype=torch.float32)
-    u = u.to(device)
+    gen = torch.Generator(device=device).manual_seed(int(seed))
+    u = torch.randn(shape, generator=gen, dtype=torch.float32, device=device)
     taps = _gauss_taps(sigma)
     half = (len(taps) - 1) // 2
     for axis in range(3):
@@ -204,6 +205,24 @@ def workload_inputs(w: Workload, device: str = "cpu"):
     else:
         raise ValueError(s["kind"])
     return n, S
+
+
+def source_tensor(w: "Workload", device: str) -> torch.Tensor:
+    """The workload's source built directly as a complex64 tensor on ``device``
+    (same values as ``workload_inputs``; avoids a host copy of large grids)."""
+    s = w.source
+    S = torch.zeros(w.shape, dtype=torch.complex64, device=device)
+    if s["kind"] == "point":
+        S[tuple(int(p) for p in s["pos"])] = 1.0
+    elif s["kind"] == "plane":
+        S[:, :, int(s["z"])] = 1.0
+    elif s["kind"] == "beam":
+        S[:, :, int(s["z"])] = torch.from_numpy(
+            gaussian_beam_source((w.shape[0], w.shape[1], 1), 0, s["waist_wavelengths"] * w.ppw)[:, :, 0]
+        ).to(device)
+    else:
+        raise ValueError(s["kind"])
+    return S
 
 
 # --------------------------------------------------------------------------

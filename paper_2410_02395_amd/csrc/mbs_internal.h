@@ -1,0 +1,131 @@
+// Internal structures shared by the HIP kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mbs {
+
+constexpr int kThreads = 256;       // threads per workgroup of every kernel (4 wavefronts)
+constexpr int kMaxT = 16;           // largest truncation t of the correction blocks
+constexpr int kHistCap = 1 << 16;   // residual history entries kept per slot
+
+// stop reasons written by the residual kernel
+enum : int32_t {
+  kRunning = 0,
+  kConverged = 1,
+  kMaxIter = 2,
+  kDiverged = 3,
+  kNonFinite = 4,
+  kIdle = 5,        // slot not participating in the current launches
+};
+
+// Per-slot iteration state, read and written on the device.
+struct SlotState {
+  double rho_ref;   // ||Gamma^-1 y|| (set from iteration 0 when it is <= 0)
+  double eps;       // relative residual of the last iteration
+  double eps_prev;
+  double rho;       // last residual norm
+  double tol;
+  int32_t iter;     // iterations completed
+  int32_t max_iter;
+  int32_t done;     // kRunning or a stop reason
+  int32_t probe;    // 1: evaluate the residual once without updating the iterate
+  double pad[2];
+};
+
+// Geometry of a plan (identical for every slot).
+struct Geo {
+  int32_t n[3];      // subdomain edge
+  int32_t P[3];      // subdomains per axis
+  int32_t a[3];      // a_d of Eq. 9 (0: no correction, 1: wrap removal, 2: split axis)
+  int32_t periodic[3];
+  int32_t N[3];      // global grid
+  int32_t t;
+  int32_t S;         // number of subdomains
+  int64_t sub_vox;   // voxels per subdomain
+  int64_t vox;       // voxels per slot (all subdomains)
+  // face update: union of the edge slabs, split into disjoint regions per axis
+  int64_t reg_count[3];  // voxels per subdomain in region d (0 if a_d == 0)
+  int32_t reg_ext[3][3]; // extents of region d along each axis
+  int32_t reg_off[3][3]; // offsets of region d along each axis (axis d itself: slab code)
+  int64_t face_vox;      // sum of reg_count (per subdomain)
+};
+
+// Per-slot pointers and scalars, in device memory (one table entry per slot).
+struct SlotDesc {
+  float2* x;              // iterate, subdomain-major [S][n0][n1][n2]
+  float2* W;              // work array (FFT in place)
+  float2* B;              // 1 - c (k^2 - k_b^2)
+  float2* slab[3][4];     // per axis: 0 X (iterate edges), 1 U (edges of u), 2 Ex, 3 Eu
+                          // each [S][2 sides][t][p][q]
+  const float2* ybox;     // -c S on the source bounding box (global coordinates)
+  int32_t ylo[3];
+  int32_t yext[3];        // 0 extent: no source
+  float c_im;             // c = i c_im
+  float alpha;            // relaxation (0 in a probe evaluation)
+  float kb2;
+  float inv_vox;          // 1 / (n0 n1 n2)
+  SlotState* st;
+  double* part_main;      // residual partials of the last inverse pass
+  double* part_face;      // residual partials of the face update
+  double* hist;           // relative residual per iteration
+  int32_t active;
+  int32_t pad;
+};
+
+// Launch helpers implemented in mbs_kernels.hip.
+struct Tables {
+  const float2* tw[3];    // forward twiddles exp(-2 pi i q / n_d), q < n_d
+  const float* p2[3];     // |p_d|^2 per Fourier index (Nyquist at -pi)
+  const float* C;         // t x t correction block (row-major C[a][b])
+};
+
+int lines_per_wg(int n);   // contiguous passes: lines per workgroup
+int cols_per_tile(int n);  // strided passes: columns (z) per tile
+bool fft_size_supported(int n);
+
+hipError_t launch_first_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
+                             hipStream_t s);
+hipError_t launch_mid_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
+                           int inverse, hipStream_t s);
+hipError_t launch_green_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
+                             hipStream_t s);
+hipError_t launch_last_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
+                            hipStream_t s);
+hipError_t launch_corr(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, int which,
+                       hipStream_t s);
+hipError_t launch_face(const SlotDesc* tab, int nslots, const Geo& g, hipStream_t s);
+hipError_t launch_reduce(const SlotDesc* tab, int nslots, const Geo& g, int64_t n_main,
+                         int64_t n_face, hipStream_t s);
+int64_t last_pass_blocks(const Geo& g);
+int64_t face_blocks(const Geo& g);
+
+// set-up kernels
+struct MediumStats {
+  double re_min, re_max, im_min;
+  double nonfinite;
+};
+hipError_t launch_medium_stats(const float2* n, const Geo& g, double k0sq, const int32_t* width,
+                               double ramp_max, MediumStats* partials, int64_t nblocks,
+                               hipStream_t s);
+hipError_t launch_medium_kmax(const float2* n, const Geo& g, double k0sq, const int32_t* width,
+                              double ramp_max, double kb2, double* partials, int64_t nblocks,
+                              hipStream_t s);
+hipError_t launch_medium_B(const float2* n, const Geo& g, double k0sq, const int32_t* width,
+                           double ramp_max, double kb2, double c_im, float2* B, hipStream_t s);
+int64_t setup_blocks(const Geo& g);
+hipError_t launch_source_bbox(const float2* S, const Geo& g, int32_t* bbox /*lo3,hi3,nonfinite*/,
+                              hipStream_t s);
+hipError_t launch_source_fill(const float2* S, const Geo& g, const int32_t* lo, const int32_t* ext,
+                              double c_im, float2* ybox, hipStream_t s);
+hipError_t launch_scatter(const float2* field, const Geo& g, float2* x, hipStream_t s);
+hipError_t launch_gather(const float2* x, const Geo& g, float2* field, hipStream_t s);
+hipError_t launch_zero(float2* p, int64_t n, hipStream_t s);
+hipError_t put_state(SlotState* dst, const SlotState& v, hipStream_t s);
+hipError_t put_desc(SlotDesc* dst, const SlotDesc& v, hipStream_t s);
+hipError_t put_i32x8(int32_t* dst, const int32_t* v, hipStream_t s);
+hipError_t launch_extract_slabs(const SlotDesc* tab, int slot, const Geo& g, int which,
+                                hipStream_t s);
+
+}  // namespace mbs

@@ -1,0 +1,1088 @@
+// HIP kernels (gfx950) of the modified Born series iteration with domain
+// decomposition (Mache & Vellekoop, arXiv 2410.02395).
+//
+// One iteration of Eq. 6 on every subdomain of every active slot:
+//   corr(X)  edge corrections of the iterate             (Sec. 3.1 steps 1-2)
+//   first    w = y + B x + Ex, FFT along z               (Eq. 6 inner (I-V)x, Eq. 5)
+//   mid      FFT along y
+//   green    FFT along x, multiply by (L+I)^-1 symbol, inverse FFT along x
+//   mid      inverse FFT along y
+//   last     inverse FFT along z, u = x - v, x -= alpha B u  (Eq. 6 outer)
+//   corr(U)  edge corrections of u
+//   face     finish x and the residual on the edge slabs (Sec. 3.1 steps 3-5)
+//   reduce   rho_n = ||d_n|| in FP64, eps_n, stop test    (Sec. 3.1 stop rule)
+// The FFTs are Stockham autosort passes (radix 8/4/3/2) over tiles staged in
+// LDS: whole lines along the contiguous axis, or N x WC column tiles along a
+// strided axis, so every global access is a coalesced row of >= 64 bytes.
+// No MFMA: nothing here is a dense contraction; the path is HBM-bound.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "mbs_internal.h"
+
+namespace mbs {
+
+// ---------------------------------------------------------------------------
+// complex helpers (float2 = interleaved re, im)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by i*SIGN  (SIGN = -1: -i, SIGN = +1: +i)
+template <int SIGN>
+__device__ __forceinline__ float2 mul_si(float2 a) {
+  return SIGN > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// (-c) z with c = i c_im
+__device__ __forceinline__ float2 mul_negc(float2 z, float c_im) {
+  return make_float2(c_im * z.y, -c_im * z.x);
+}
+
+// ---------------------------------------------------------------------------
+// DFT butterflies; SIGN = -1 forward (exp(-2 pi i jk/R)), +1 inverse
+// ---------------------------------------------------------------------------
+template <int SIGN, int R>
+struct Bfly;
+
+template <int SIGN>
+struct Bfly<SIGN, 2> {
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+  }
+};
+
+template <int SIGN>
+struct Bfly<SIGN, 3> {
+  __device__ __forceinline__ static void run(float2* v) {
+    const float h = 0.86602540378443864676f;  // sqrt(3)/2
+    float2 s = cadd(v[1], v[2]);
+    float2 d = csub(v[1], v[2]);
+    float2 t = make_float2(v[0].x - 0.5f * s.x, v[0].y - 0.5f * s.y);
+    float2 r = mul_si<SIGN>(cscale(d, h));
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(t, r);
+    v[2] = csub(t, r);
+  }
+};
+
+template <int SIGN>
+struct Bfly<SIGN, 4> {
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 t0 = cadd(v[0], v[2]);
+    float2 t1 = csub(v[0], v[2]);
+    float2 t2 = cadd(v[1], v[3]);
+    float2 t3 = mul_si<SIGN>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+
+template <int SIGN>
+struct Bfly<SIGN, 8> {
+  __device__ __forceinline__ static void run(float2* v) {
+    const float r = 0.70710678118654752440f;
+    float2 a[4], b[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      a[m] = cadd(v[m], v[m + 4]);
+      b[m] = csub(v[m], v[m + 4]);
+    }
+    // b_m *= w8^(SIGN*m), w8 = exp(i pi/4)
+    {
+      float2 z = b[1];  // * (1 + SIGN i)/sqrt2
+      b[1] = SIGN > 0 ? make_float2(r * (z.x - z.y), r * (z.x + z.y))
+                      : make_float2(r * (z.x + z.y), r * (z.y - z.x));
+      b[2] = mul_si<SIGN>(b[2]);
+      z = b[3];  // * (-1 + SIGN i)/sqrt2
+      b[3] = SIGN > 0 ? make_float2(-r * (z.x + z.y), r * (z.x - z.y))
+                      : make_float2(r * (z.y - z.x), -r * (z.x + z.y));
+    }
+    Bfly<SIGN, 4>::run(a);
+    Bfly<SIGN, 4>::run(b);
+    v[0] = a[0]; v[2] = a[1]; v[4] = a[2]; v[6] = a[3];
+    v[1] = b[0]; v[3] = b[1]; v[5] = b[2]; v[7] = b[3];
+  }
+};
+
+// radix of the next Stockham stage for the remaining length
+__host__ __device__ constexpr int radix_of(int rem) {
+  return rem % 3 == 0 ? 3 : (rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : 2));
+}
+
+// ---------------------------------------------------------------------------
+// tile layouts in LDS
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int lines_per_wg_c(int n) { return n >= 2048 ? 1 : 2048 / n; }
+__host__ __device__ constexpr int cols_per_tile_c(int n) {
+  return n >= 768 ? 8 : (n >= 128 ? 16 : (n >= 64 ? 32 : 64));
+}
+
+// LINES whole lines of N contiguous elements; element (j, l) at l*N + j, padded by one
+// slot every 16 to spread the stride-R writes of the first stage over the banks.
+template <int N, int LINES>
+struct LineTile {
+  static constexpr int ELEMS = N * LINES;
+  static constexpr int LDS = ELEMS + ELEMS / 16 + 1;
+  __device__ __forceinline__ static int idx(int j, int l) {
+    int f = l * N + j;
+    return f + (f >> 4);
+  }
+  template <int R>
+  __device__ __forceinline__ static void bf(int b, int& i, int& l) {
+    i = b % (N / R);
+    l = b / (N / R);
+  }
+  template <int R>
+  static constexpr int nb() { return (N / R) * LINES; }
+};
+
+// N rows (the FFT axis) x WC contiguous columns; element (j, c) at j*WC + c.
+template <int N, int WC>
+struct ColTile {
+  static constexpr int ELEMS = N * WC;
+  static constexpr int LDS = ELEMS;
+  __device__ __forceinline__ static int idx(int j, int c) { return j * WC + c; }
+  template <int R>
+  __device__ __forceinline__ static void bf(int b, int& i, int& c) {
+    c = b % WC;
+    i = b / WC;
+  }
+  template <int R>
+  static constexpr int nb() { return (N / R) * WC; }
+};
+
+// One radix-R Stockham stage in place in LDS (read all, barrier, write all, barrier).
+// Butterfly i (of N/R per line) reads elements i + m N/R, multiplies input m by
+// w^(m k) (k = i mod NS, w = exp(SIGN 2 pi i / (NS R))), and writes output m to
+// (i - k) R + k + m NS.
+template <class Tile, int N, int R, int NS, int SIGN>
+__device__ __forceinline__ void stockham_stage(float2* lds, const float2* __restrict__ tw, int tid) {
+  constexpr int NB = Tile::template nb<R>();
+  constexpr int PER = (NB + kThreads - 1) / kThreads;
+  constexpr int STRIDE = N / R;
+  float2 v[PER][R];
+  int ob[PER], lb[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = tid + q * kThreads;
+    if ((NB % kThreads) == 0 || b < NB) {
+      int i, l;
+      Tile::template bf<R>(b, i, l);
+      const int k = i % NS;
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[q][m] = lds[Tile::idx(i + m * STRIDE, l)];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int m = 1; m < R; ++m) {
+          float2 w = tw[(m * k) * (N / (NS * R))];
+          if (SIGN > 0) w.y = -w.y;
+          v[q][m] = cmul(v[q][m], w);
+        }
+      }
+      Bfly<SIGN, R>::run(v[q]);
+      ob[q] = (i - k) * R + k;
+      lb[q] = l;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = tid + q * kThreads;
+    if ((NB % kThreads) == 0 || b < NB) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[Tile::idx(ob[q] + m * NS, lb[q])] = v[q][m];
+    }
+  }
+  __syncthreads();
+}
+
+template <class Tile, int N, int NS, int SIGN>
+__device__ __forceinline__ void fft_stages(float2* lds, const float2* __restrict__ tw, int tid) {
+  if constexpr (NS < N) {
+    constexpr int R = radix_of(N / NS);
+    stockham_stage<Tile, N, R, NS, SIGN>(lds, tw, tid);
+    fft_stages<Tile, N, NS * R, SIGN>(lds, tw, tid);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// block reduction of one double per thread (fixed order: deterministic)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+  }
+  return s;  // valid on thread 0
+}
+
+// ---------------------------------------------------------------------------
+// per-line bookkeeping of the contiguous (z) passes
+// ---------------------------------------------------------------------------
+struct LineInfo {
+  int64_t gbase;   // index of element 0 of the line in the subdomain-major arrays
+  int64_t e0;      // slab offset for axis 0 (element j at e0 + j), -1 if not in a slab
+  int64_t e1;      // slab offset for axis 1, -1 if not in a slab
+  int64_t e2;      // slab offset for axis 2 at depth 0 of side 0 (-1: axis not corrected)
+  int64_t ybase;   // source box index of element j (ybase + j), valid for j in [jlo, jhi)
+  int32_t jlo, jhi;
+  int32_t valid;
+  int32_t pad;
+};
+
+__device__ __forceinline__ void line_info(int64_t line, const Geo& g, const SlotDesc& sd,
+                                          LineInfo& li) {
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], t = g.t;
+  const int64_t nlines = (int64_t)g.S * n0 * n1;
+  li.valid = line < nlines;
+  if (!li.valid) return;
+  const int i1 = (int)(line % n1);
+  const int64_t r = line / n1;
+  const int i0 = (int)(r % n0);
+  const int s = (int)(r / n0);
+  li.gbase = line * n2;
+  li.e0 = -1;
+  li.e1 = -1;
+  li.e2 = -1;
+  if (g.a[0] > 0 && (i0 < t || i0 >= n0 - t)) {
+    const int side = i0 < t ? 0 : 1;
+    const int aa = side ? i0 - (n0 - t) : i0;
+    li.e0 = (((int64_t)s * 2 + side) * t + aa) * ((int64_t)n1 * n2) + (int64_t)i1 * n2;
+  }
+  if (g.a[1] > 0 && (i1 < t || i1 >= n1 - t)) {
+    const int side = i1 < t ? 0 : 1;
+    const int aa = side ? i1 - (n1 - t) : i1;
+    li.e1 = (((int64_t)s * 2 + side) * t + aa) * ((int64_t)n0 * n2) + (int64_t)i0 * n2;
+  }
+  if (g.a[2] > 0) li.e2 = ((int64_t)s * 2 * t) * ((int64_t)n0 * n1) + (int64_t)i0 * n1 + i1;
+  // source box (global coordinates)
+  li.jlo = 0;
+  li.jhi = 0;
+  li.ybase = 0;
+  if (sd.yext[0] > 0) {
+    const int s2 = s % g.P[2];
+    const int s1 = (s / g.P[2]) % g.P[1];
+    const int s0 = s / (g.P[2] * g.P[1]);
+    const int g0 = s0 * n0 + i0 - sd.ylo[0];
+    const int g1 = s1 * n1 + i1 - sd.ylo[1];
+    if (g0 >= 0 && g0 < sd.yext[0] && g1 >= 0 && g1 < sd.yext[1]) {
+      const int z0 = s2 * n2;  // global z of local j = 0
+      int lo = sd.ylo[2] - z0;
+      int hi = sd.ylo[2] + sd.yext[2] - z0;
+      lo = lo < 0 ? 0 : lo;
+      hi = hi > n2 ? n2 : hi;
+      if (lo < hi) {
+        li.jlo = lo;
+        li.jhi = hi;
+        li.ybase = ((int64_t)g0 * sd.yext[1] + g1) * sd.yext[2] + (z0 - sd.ylo[2]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// first pass: w = y + B x + sum_d Ex_d, forward FFT along z
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_first(const SlotDesc* __restrict__ tab, Geo g,
+                                                    Tables tb) {
+  const SlotDesc sd = tab[blockIdx.y];
+  if (sd.st->done != kRunning) return;
+  constexpr int L = lines_per_wg_c(N);
+  using Tile = LineTile<N, L>;
+  __shared__ float2 lds[Tile::LDS];
+  __shared__ LineInfo info[L];
+  const int tid = threadIdx.x;
+  const int64_t line0 = (int64_t)blockIdx.x * L;
+  for (int l = tid; l < L; l += kThreads) line_info(line0 + l, g, sd, info[l]);
+  __syncthreads();
+  const int t = g.t;
+  const int64_t plane2 = (int64_t)g.n[0] * g.n[1];
+  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
+    const int l = f / N;
+    const int j = f - l * N;
+    const LineInfo& li = info[l];
+    float2 w = make_float2(0.f, 0.f);
+    if (li.valid) {
+      const int64_t gi = li.gbase + j;
+      w = cmul(sd.B[gi], sd.x[gi]);
+      if (li.e0 >= 0) w = cadd(w, sd.slab[0][2][li.e0 + j]);
+      if (li.e1 >= 0) w = cadd(w, sd.slab[1][2][li.e1 + j]);
+      if (li.e2 >= 0) {
+        if (j < t) w = cadd(w, sd.slab[2][2][li.e2 + (int64_t)j * plane2]);
+        else if (j >= N - t) w = cadd(w, sd.slab[2][2][li.e2 + (int64_t)(t + j - (N - t)) * plane2]);
+      }
+      if (j >= li.jlo && j < li.jhi) w = cadd(w, sd.ybox[li.ybase + j]);
+    }
+    lds[Tile::idx(j, l)] = w;
+  }
+  __syncthreads();
+  fft_stages<Tile, N, 1, -1>(lds, tb.tw[2], tid);
+  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
+    const int l = f / N;
+    const int j = f - l * N;
+    if (info[l].valid) sd.W[info[l].gbase + j] = lds[Tile::idx(j, l)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// last pass: inverse FFT along z, u = x - v, x -= alpha B u, edge slabs of u,
+// residual partial sum of |B u|^2 over voxels outside every edge slab
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ tab, Geo g,
+                                                   Tables tb) {
+  const SlotDesc sd = tab[blockIdx.y];
+  if (sd.st->done != kRunning) return;
+  constexpr int L = lines_per_wg_c(N);
+  using Tile = LineTile<N, L>;
+  __shared__ float2 lds[Tile::LDS];
+  __shared__ LineInfo info[L];
+  __shared__ double red[kThreads / 64];
+  const int tid = threadIdx.x;
+  const int64_t line0 = (int64_t)blockIdx.x * L;
+  for (int l = tid; l < L; l += kThreads) line_info(line0 + l, g, sd, info[l]);
+  __syncthreads();
+  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
+    const int l = f / N;
+    const int j = f - l * N;
+    lds[Tile::idx(j, l)] = info[l].valid ? sd.W[info[l].gbase + j] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_stages<Tile, N, 1, +1>(lds, tb.tw[2], tid);
+  const int t = g.t;
+  const int64_t plane2 = (int64_t)g.n[0] * g.n[1];
+  const float alpha = sd.alpha;
+  double acc = 0.0;
+  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
+    const int l = f / N;
+    const int j = f - l * N;
+    const LineInfo& li = info[l];
+    if (!li.valid) continue;
+    const int64_t gi = li.gbase + j;
+    const float2 v = lds[Tile::idx(j, l)];
+    const float2 xv = sd.x[gi];
+    const float2 u = csub(xv, v);
+    const float2 bu = cmul(sd.B[gi], u);
+    sd.x[gi] = make_float2(xv.x - alpha * bu.x, xv.y - alpha * bu.y);
+    bool edge = false;
+    if (li.e0 >= 0) { sd.slab[0][1][li.e0 + j] = u; edge = true; }
+    if (li.e1 >= 0) { sd.slab[1][1][li.e1 + j] = u; edge = true; }
+    if (li.e2 >= 0) {
+      if (j < t) { sd.slab[2][1][li.e2 + (int64_t)j * plane2] = u; edge = true; }
+      else if (j >= N - t) { sd.slab[2][1][li.e2 + (int64_t)(t + j - (N - t)) * plane2] = u; edge = true; }
+    }
+    if (!edge) acc += (double)bu.x * bu.x + (double)bu.y * bu.y;
+  }
+  const double s = block_sum(acc, red);
+  if (tid == 0) sd.part_main[blockIdx.x] = s;
+}
+
+// ---------------------------------------------------------------------------
+// strided passes: FFT along y (mid) or x (green, with the (L+I)^-1 symbol)
+// ---------------------------------------------------------------------------
+template <int N, int SIGN>
+__global__ __launch_bounds__(kThreads) void k_mid(const SlotDesc* __restrict__ tab, Geo g, Tables tb) {
+  const SlotDesc sd = tab[blockIdx.y];
+  if (sd.st->done != kRunning) return;
+  constexpr int WC = cols_per_tile_c(N);
+  using Tile = ColTile<N, WC>;
+  __shared__ float2 lds[Tile::LDS];
+  const int tid = threadIdx.x;
+  const int n0 = g.n[0], n2 = g.n[2];
+  const int CB = (n2 + WC - 1) / WC;
+  const int cb = blockIdx.x % CB;
+  const int64_t rest = blockIdx.x / CB;
+  const int i0 = (int)(rest % n0);
+  const int s = (int)(rest / n0);
+  const int c0 = cb * WC;
+  const int ncols = min(WC, n2 - c0);
+  const int64_t base = (((int64_t)s * n0 + i0) * N) * n2 + c0;
+  const int64_t stride = n2;
+  float2* __restrict__ W = sd.W;
+  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
+    const int c = f % WC;
+    const int j = f / WC;
+    lds[Tile::idx(j, c)] = c < ncols ? W[base + j * stride + c] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_stages<Tile, N, 1, SIGN>(lds, tb.tw[1], tid);
+  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
+    const int c = f % WC;
+    const int j = f / WC;
+    if (c < ncols) W[base + j * stride + c] = lds[Tile::idx(j, c)];
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_green(const SlotDesc* __restrict__ tab, Geo g, Tables tb) {
+  const SlotDesc sd = tab[blockIdx.y];
+  if (sd.st->done != kRunning) return;
+  constexpr int WC = cols_per_tile_c(N);
+  using Tile = ColTile<N, WC>;
+  __shared__ float2 lds[Tile::LDS];
+  const int tid = threadIdx.x;
+  const int n1 = g.n[1], n2 = g.n[2];
+  const int CB = (n2 + WC - 1) / WC;
+  const int cb = blockIdx.x % CB;
+  const int64_t rest = blockIdx.x / CB;
+  const int i1 = (int)(rest % n1);
+  const int s = (int)(rest / n1);
+  const int c0 = cb * WC;
+  const int ncols = min(WC, n2 - c0);
+  const int64_t base = ((int64_t)s * N * n1 + i1) * n2 + c0;
+  const int64_t stride = (int64_t)n1 * n2;
+  float2* __restrict__ W = sd.W;
+  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
+    const int c = f % WC;
+    const int j = f / WC;
+    lds[Tile::idx(j, c)] = c < ncols ? W[base + j * stride + c] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_stages<Tile, N, 1, -1>(lds, tb.tw[0], tid);
+  // (L + I)^-1 = 1 / (1 + c (k_b^2 - |p|^2)), c = i c_im, with the 1/(n0 n1 n2) of the inverse
+  {
+    const float p21 = tb.p2[1][i1];
+    const float kb2 = sd.kb2, cim = sd.c_im, inv = sd.inv_vox;
+    for (int f = tid; f < Tile::ELEMS; f += kThreads) {
+      const int c = f % WC;
+      const int j = f / WC;
+      const int cz = c < ncols ? c0 + c : 0;
+      const float P = tb.p2[0][j] + p21 + tb.p2[2][cz];
+      const float E = cim * (kb2 - P);
+      const float den = inv / (1.f + E * E);
+      const float2 G = make_float2(den, -E * den);
+      const int ix = Tile::idx(j, c);
+      lds[ix] = cmul(lds[ix], G);
+    }
+  }
+  __syncthreads();
+  fft_stages<Tile, N, 1, +1>(lds, tb.tw[0], tid);
+  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
+    const int c = f % WC;
+    const int j = f / WC;
+    if (c < ncols) W[base + j * stride + c] = lds[Tile::idx(j, c)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// edge corrections along one axis: for each line, from the first t (l) and
+// last t (h) values of the subdomain and its neighbours,
+//   E_lo[a] = -c (C (h_{s-1} - h_s))[a],   E_hi[a] = -c (C^T (l_{s+1} - l_s))[a]
+// with absent neighbours contributing zero (Sec. 3 and Sec. 3.1 steps 1-5).
+// which = 0: X -> Ex (iterate), 1: U -> Eu (u = x - v).
+// ---------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(kThreads) void k_corr(const SlotDesc* __restrict__ tab, Geo g,
+                                                   const float* __restrict__ C, int d, int which) {
+  const SlotDesc& sd = tab[blockIdx.y];
+  if (sd.st->done != kRunning) return;
+  const int64_t plane = d == 0 ? (int64_t)g.n[1] * g.n[2]
+                               : (d == 1 ? (int64_t)g.n[0] * g.n[2] : (int64_t)g.n[0] * g.n[1]);
+  const int64_t L = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (L >= (int64_t)g.S * plane) return;
+  const int s = (int)(L / plane);
+  const int64_t pq = L - (int64_t)s * plane;
+  int sc[3];
+  sc[2] = s % g.P[2];
+  sc[1] = (s / g.P[2]) % g.P[1];
+  sc[0] = s / (g.P[2] * g.P[1]);
+  const int Pd = g.P[d];
+  const bool cyc = g.periodic[d] && Pd >= 2;
+  const bool has_lo = Pd >= 2 && (sc[d] > 0 || cyc);
+  const bool has_hi = Pd >= 2 && (sc[d] < Pd - 1 || cyc);
+  const int mul = d == 0 ? g.P[1] * g.P[2] : (d == 1 ? g.P[2] : 1);
+  const int s_lo = s + (((sc[d] - 1 + Pd) % Pd) - sc[d]) * mul;
+  const int s_hi = s + (((sc[d] + 1) % Pd) - sc[d]) * mul;
+  const float2* __restrict__ src = sd.slab[d][which == 0 ? 0 : 1];
+  float2* __restrict__ dst = sd.slab[d][which == 0 ? 2 : 3];
+  float2 dh[T], dl[T];
+#pragma unroll
+  for (int b = 0; b < T; ++b) {
+    const float2 h = src[(((int64_t)s * 2 + 1) * T + b) * plane + pq];
+    const float2 l = src[(((int64_t)s * 2 + 0) * T + b) * plane + pq];
+    const float2 hn = has_lo ? src[(((int64_t)s_lo * 2 + 1) * T + b) * plane + pq] : make_float2(0.f, 0.f);
+    const float2 ln = has_hi ? src[(((int64_t)s_hi * 2 + 0) * T + b) * plane + pq] : make_float2(0.f, 0.f);
+    dh[b] = csub(hn, h);
+    dl[b] = csub(ln, l);
+  }
+  const float cim = sd.c_im;
+#pragma unroll
+  for (int a = 0; a < T; ++a) {
+    float2 elo = make_float2(0.f, 0.f), ehi = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int b = 0; b < T; ++b) {
+      const float cab = C[a * T + b];
+      const float cba = C[b * T + a];
+      elo.x += cab * dh[b].x;
+      elo.y += cab * dh[b].y;
+      ehi.x += cba * dl[b].x;
+      ehi.y += cba * dl[b].y;
+    }
+    dst[(((int64_t)s * 2 + 0) * T + a) * plane + pq] = mul_negc(elo, cim);
+    dst[(((int64_t)s * 2 + 1) * T + a) * plane + pq] = mul_negc(ehi, cim);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// face update over the union of the edge slabs (disjoint regions per axis):
+//   d = B u + sum Eu,  x -= alpha sum Eu,  X slabs <- x,  partial sum |d|^2
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_face(const SlotDesc* __restrict__ tab, Geo g) {
+  const SlotDesc sd = tab[blockIdx.y];
+  if (sd.st->done != kRunning) return;
+  __shared__ double red[kThreads / 64];
+  const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double acc = 0.0;
+  if (gid < (int64_t)g.S * g.face_vox) {
+    const int s = (int)(gid / g.face_vox);
+    int64_t r = gid - (int64_t)s * g.face_vox;
+    int reg = 0;
+    while (r >= g.reg_count[reg]) {
+      r -= g.reg_count[reg];
+      ++reg;
+    }
+    const int e2 = (int)(r % g.reg_ext[reg][2]);
+    r /= g.reg_ext[reg][2];
+    const int e1 = (int)(r % g.reg_ext[reg][1]);
+    const int e0 = (int)(r / g.reg_ext[reg][1]);
+    int e[3] = {e0, e1, e2};
+    int i[3];
+    const int t = g.t;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k == reg) i[k] = e[k] < t ? e[k] : g.n[k] - 2 * t + e[k];
+      else i[k] = e[k] + g.reg_off[reg][k];
+    }
+    float2 esum = make_float2(0.f, 0.f), u = make_float2(0.f, 0.f);
+    int64_t addr[3] = {-1, -1, -1};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (g.a[k] == 0) continue;
+      int side, aa;
+      if (i[k] < t) { side = 0; aa = i[k]; }
+      else if (i[k] >= g.n[k] - t) { side = 1; aa = i[k] - (g.n[k] - t); }
+      else continue;
+      const int p = k == 0 ? i[1] : i[0];
+      const int q = k == 2 ? i[1] : i[2];
+      const int dq = k == 2 ? g.n[1] : g.n[2];
+      const int64_t plane = k == 0 ? (int64_t)g.n[1] * g.n[2]
+                                   : (k == 1 ? (int64_t)g.n[0] * g.n[2] : (int64_t)g.n[0] * g.n[1]);
+      const int64_t ad = (((int64_t)s * 2 + side) * t + aa) * plane + (int64_t)p * dq + q;
+      addr[k] = ad;
+      esum = cadd(esum, sd.slab[k][3][ad]);
+      u = sd.slab[k][1][ad];
+    }
+    const int64_t gi = (((int64_t)s * g.n[0] + i[0]) * g.n[1] + i[1]) * g.n[2] + i[2];
+    const float2 bu = cmul(sd.B[gi], u);
+    const float2 dd = cadd(bu, esum);
+    const float2 xv = sd.x[gi];
+    const float2 xn = make_float2(xv.x - sd.alpha * esum.x, xv.y - sd.alpha * esum.y);
+    sd.x[gi] = xn;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (addr[k] >= 0) sd.slab[k][0][addr[k]] = xn;
+    acc = (double)dd.x * dd.x + (double)dd.y * dd.y;
+  }
+  const double ssum = block_sum(acc, red);
+  if (threadIdx.x == 0) sd.part_face[blockIdx.x] = ssum;
+}
+
+// ---------------------------------------------------------------------------
+// residual norm, relative residual and stop test (one workgroup per slot)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_reduce(const SlotDesc* __restrict__ tab, int64_t n_main,
+                                                     int64_t n_face) {
+  const SlotDesc sd = tab[blockIdx.x];
+  SlotState* st = sd.st;
+  if (st->done != kRunning) return;
+  __shared__ double red[kThreads / 64];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n_main; i += kThreads) acc += sd.part_main[i];
+  for (int64_t i = threadIdx.x; i < n_face; i += kThreads) acc += sd.part_face[i];
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x != 0) return;
+  const double rho = sqrt(tot);
+  st->rho = rho;
+  if (st->probe) {
+    st->done = isfinite(rho) ? kConverged : kNonFinite;
+    return;
+  }
+  const int it = st->iter;
+  if (it == 0 && !(st->rho_ref > 0.0)) st->rho_ref = rho;
+  const double eps = st->rho_ref > 0.0 ? rho / st->rho_ref : 0.0;
+  if (it < kHistCap) sd.hist[it] = eps;
+  st->iter = it + 1;
+  st->eps = eps;
+  if (!isfinite(rho)) st->done = kNonFinite;
+  else if (eps < st->tol) st->done = kConverged;
+  else if (it > 0 && st->eps_prev > 1e-5 && eps > st->eps_prev * 1.01) st->done = kDiverged;
+  else if (it + 1 >= st->max_iter) st->done = kMaxIter;
+  st->eps_prev = eps;
+}
+
+// ---------------------------------------------------------------------------
+// set-up kernels (FP64 medium statistics, operator diagonal, source, layout)
+// ---------------------------------------------------------------------------
+struct Int3 { int32_t v[3]; };
+
+__device__ __forceinline__ void global_coords(int64_t v, const Geo& g, int& g0, int& g1, int& g2) {
+  g2 = (int)(v % g.N[2]);
+  const int64_t r = v / g.N[2];
+  g1 = (int)(r % g.N[1]);
+  g0 = (int)(r / g.N[1]);
+}
+
+__device__ __forceinline__ int64_t local_index(int g0, int g1, int g2, const Geo& g) {
+  const int s0 = g0 / g.n[0], s1 = g1 / g.n[1], s2 = g2 / g.n[2];
+  const int i0 = g0 - s0 * g.n[0], i1 = g1 - s1 * g.n[1], i2 = g2 - s2 * g.n[2];
+  const int s = (s0 * g.P[1] + s1) * g.P[2] + s2;
+  return (((int64_t)s * g.n[0] + i0) * g.n[1] + i1) * g.n[2] + i2;
+}
+
+// Im(n^2) of the absorbing layer: linear ramp over the outermost W voxels of each side,
+// maximum over axes
+__device__ __forceinline__ double ramp_at(int g0, int g1, int g2, const Geo& g, const Int3& w,
+                                          double rmax) {
+  const int gc[3] = {g0, g1, g2};
+  double r = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int W = w.v[d];
+    if (W <= 0) continue;
+    const int i = gc[d];
+    if (i < W) r = fmax(r, rmax * (double)(W - i) / (double)W);
+    if (i >= g.N[d] - W) r = fmax(r, rmax * (double)(i - (g.N[d] - W) + 1) / (double)W);
+  }
+  return r;
+}
+
+__device__ __forceinline__ void wavenumber_sq(const float2* n, int64_t v, const Geo& g, double k0sq,
+                                              const Int3& w, double rmax, double& re, double& im,
+                                              bool& finite) {
+  const float2 nv = n[v];
+  const double nr = nv.x, ni = nv.y;
+  finite = isfinite(nr) && isfinite(ni);
+  int g0, g1, g2;
+  global_coords(v, g, g0, g1, g2);
+  const double n2r = nr * nr - ni * ni;
+  const double n2i = nr * ni + ni * nr + ramp_at(g0, g1, g2, g, w, rmax);
+  re = k0sq * n2r;
+  im = k0sq * n2i;
+}
+
+__global__ __launch_bounds__(kThreads) void k_medium_stats(const float2* __restrict__ n, Geo g,
+                                                           double k0sq, Int3 w, double rmax,
+                                                           MediumStats* part) {
+  __shared__ double smin[kThreads], smax[kThreads], simin[kThreads], snf[kThreads];
+  double mn = INFINITY, mx = -INFINITY, imn = INFINITY, nf = 0.0;
+  for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < g.vox;
+       v += (int64_t)gridDim.x * kThreads) {
+    double re, im;
+    bool fin;
+    wavenumber_sq(n, v, g, k0sq, w, rmax, re, im, fin);
+    if (!fin) { nf += 1.0; continue; }
+    mn = fmin(mn, re);
+    mx = fmax(mx, re);
+    imn = fmin(imn, im);
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  simin[threadIdx.x] = imn;
+  snf[threadIdx.x] = nf;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + off]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + off]);
+      simin[threadIdx.x] = fmin(simin[threadIdx.x], simin[threadIdx.x + off]);
+      snf[threadIdx.x] += snf[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x].re_min = smin[0];
+    part[blockIdx.x].re_max = smax[0];
+    part[blockIdx.x].im_min = simin[0];
+    part[blockIdx.x].nonfinite = snf[0];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_medium_kmax(const float2* __restrict__ n, Geo g,
+                                                          double k0sq, Int3 w, double rmax,
+                                                          double kb2, double* part) {
+  __shared__ double sm[kThreads];
+  double mx = 0.0;
+  for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < g.vox;
+       v += (int64_t)gridDim.x * kThreads) {
+    double re, im;
+    bool fin;
+    wavenumber_sq(n, v, g, k0sq, w, rmax, re, im, fin);
+    mx = fmax(mx, hypot(re - kb2, im));
+  }
+  sm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+// B = 1 - c (k^2 - k_b^2), c = i c_im, written subdomain-major
+__global__ __launch_bounds__(kThreads) void k_medium_B(const float2* __restrict__ n, Geo g, double k0sq,
+                                                       Int3 w, double rmax, double kb2, double c_im,
+                                                       float2* __restrict__ B) {
+  for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < g.vox;
+       v += (int64_t)gridDim.x * kThreads) {
+    double re, im;
+    bool fin;
+    wavenumber_sq(n, v, g, k0sq, w, rmax, re, im, fin);
+    const double zr = re - kb2, zi = im;
+    int g0, g1, g2;
+    global_coords(v, g, g0, g1, g2);
+    B[local_index(g0, g1, g2, g)] = make_float2((float)(1.0 + c_im * zi), (float)(-c_im * zr));
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_source_bbox(const float2* __restrict__ S, Geo g,
+                                                          int32_t* bbox) {
+  for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < g.vox;
+       v += (int64_t)gridDim.x * kThreads) {
+    const float2 s = S[v];
+    if (!(isfinite(s.x) && isfinite(s.y))) {
+      atomicOr(&bbox[6], 1);
+      continue;
+    }
+    if (s.x == 0.f && s.y == 0.f) continue;
+    int gc[3];
+    global_coords(v, g, gc[0], gc[1], gc[2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      atomicMin(&bbox[d], gc[d]);
+      atomicMax(&bbox[3 + d], gc[d]);
+    }
+  }
+}
+
+// y = -c S on the bounding box, box-local C-order
+__global__ __launch_bounds__(kThreads) void k_source_fill(const float2* __restrict__ S, Geo g, Int3 lo,
+                                                          Int3 ext, double c_im, float2* __restrict__ y) {
+  const int64_t nb = (int64_t)ext.v[0] * ext.v[1] * ext.v[2];
+  const float cim = (float)c_im;
+  for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < nb;
+       v += (int64_t)gridDim.x * kThreads) {
+    const int b2 = (int)(v % ext.v[2]);
+    const int64_t r = v / ext.v[2];
+    const int b1 = (int)(r % ext.v[1]);
+    const int b0 = (int)(r / ext.v[1]);
+    const int64_t gv = ((int64_t)(b0 + lo.v[0]) * g.N[1] + (b1 + lo.v[1])) * g.N[2] + (b2 + lo.v[2]);
+    y[v] = mul_negc(S[gv], cim);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scatter(const float2* __restrict__ f, Geo g,
+                                                      float2* __restrict__ x) {
+  for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < g.vox;
+       v += (int64_t)gridDim.x * kThreads) {
+    int g0, g1, g2;
+    global_coords(v, g, g0, g1, g2);
+    x[local_index(g0, g1, g2, g)] = f[v];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_gather(const float2* __restrict__ x, Geo g,
+                                                     float2* __restrict__ f) {
+  for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < g.vox;
+       v += (int64_t)gridDim.x * kThreads) {
+    int g0, g1, g2;
+    global_coords(v, g, g0, g1, g2);
+    f[v] = x[local_index(g0, g1, g2, g)];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero(float2* __restrict__ p, int64_t n) {
+  for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * kThreads)
+    p[v] = make_float2(0.f, 0.f);
+}
+
+// copy the edge slabs of the iterate (which = 0 -> X) of one slot from x
+__global__ __launch_bounds__(kThreads) void k_extract(const SlotDesc* __restrict__ tab, int slot, Geo g,
+                                                     int d) {
+  const SlotDesc sd = tab[slot];
+  const int t = g.t;
+  const int64_t plane = d == 0 ? (int64_t)g.n[1] * g.n[2]
+                               : (d == 1 ? (int64_t)g.n[0] * g.n[2] : (int64_t)g.n[0] * g.n[1]);
+  const int64_t total = (int64_t)g.S * 2 * t * plane;
+  for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < total;
+       v += (int64_t)gridDim.x * kThreads) {
+    const int64_t pq = v % plane;
+    const int64_t r = v / plane;
+    const int aa = (int)(r % t);
+    const int side = (int)((r / t) % 2);
+    const int s = (int)(r / (2 * t));
+    const int pos = side ? g.n[d] - t + aa : aa;
+    const int dq = d == 2 ? g.n[1] : g.n[2];
+    const int p = (int)(pq / dq);
+    const int q = (int)(pq % dq);
+    int i[3];
+    i[d] = pos;
+    if (d == 0) { i[1] = p; i[2] = q; }
+    else if (d == 1) { i[0] = p; i[2] = q; }
+    else { i[0] = p; i[1] = q; }
+    const int64_t gi = (((int64_t)s * g.n[0] + i[0]) * g.n[1] + i[1]) * g.n[2] + i[2];
+    sd.slab[d][0][v] = sd.x[gi];
+  }
+}
+
+// small stream-ordered control writes (values travel as kernel arguments)
+__global__ void k_put_state(SlotState* dst, SlotState v) {
+  if (threadIdx.x == 0) *dst = v;
+}
+__global__ void k_put_desc(SlotDesc* dst, SlotDesc v) {
+  if (threadIdx.x == 0) *dst = v;
+}
+struct Int8 { int32_t v[8]; };
+__global__ void k_put_i32x8(int32_t* dst, Int8 v) {
+  if (threadIdx.x < 8) dst[threadIdx.x] = v.v[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t put_state(SlotState* dst, const SlotState& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_put_state, dim3(1), dim3(64), 0, s, dst, v);
+  return hipGetLastError();
+}
+hipError_t put_desc(SlotDesc* dst, const SlotDesc& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, dst, v);
+  return hipGetLastError();
+}
+hipError_t put_i32x8(int32_t* dst, const int32_t* v, hipStream_t s) {
+  Int8 w;
+  for (int i = 0; i < 8; ++i) w.v[i] = v[i];
+  hipLaunchKernelGGL(k_put_i32x8, dim3(1), dim3(64), 0, s, dst, w);
+  return hipGetLastError();
+}
+
+int lines_per_wg(int n) { return lines_per_wg_c(n); }
+int cols_per_tile(int n) { return cols_per_tile_c(n); }
+
+#define MBS_FOR_EACH_N(X) \
+  X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+
+bool fft_size_supported(int n) {
+  switch (n) {
+#define MBS_CASE(NN) case NN:
+    MBS_FOR_EACH_N(MBS_CASE)
+#undef MBS_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+static inline unsigned grid_1d(int64_t work, int64_t cap = 1 << 20) {
+  int64_t b = (work + kThreads - 1) / kThreads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+int64_t last_pass_blocks(const Geo& g) {
+  const int64_t lines = (int64_t)g.S * g.n[0] * g.n[1];
+  const int L = lines_per_wg_c(g.n[2]);
+  return (lines + L - 1) / L;
+}
+
+int64_t face_blocks(const Geo& g) {
+  return ((int64_t)g.S * g.face_vox + kThreads - 1) / kThreads;
+}
+
+hipError_t launch_first_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
+                             hipStream_t s) {
+  dim3 grid((unsigned)last_pass_blocks(g), nslots);
+  switch (g.n[2]) {
+#define MBS_CASE(NN) \
+  case NN: hipLaunchKernelGGL(k_first<NN>, grid, dim3(kThreads), 0, s, tab, g, tb); break;
+    MBS_FOR_EACH_N(MBS_CASE)
+#undef MBS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_last_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
+                            hipStream_t s) {
+  dim3 grid((unsigned)last_pass_blocks(g), nslots);
+  switch (g.n[2]) {
+#define MBS_CASE(NN) \
+  case NN: hipLaunchKernelGGL(k_last<NN>, grid, dim3(kThreads), 0, s, tab, g, tb); break;
+    MBS_FOR_EACH_N(MBS_CASE)
+#undef MBS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mid_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
+                           int inverse, hipStream_t s) {
+  const int WC = cols_per_tile_c(g.n[1]);
+  const int64_t blocks = (int64_t)g.S * g.n[0] * ((g.n[2] + WC - 1) / WC);
+  dim3 grid((unsigned)blocks, nslots);
+  switch (g.n[1]) {
+#define MBS_CASE(NN)                                                                  \
+  case NN:                                                                            \
+    if (inverse) hipLaunchKernelGGL((k_mid<NN, 1>), grid, dim3(kThreads), 0, s, tab, g, tb); \
+    else hipLaunchKernelGGL((k_mid<NN, -1>), grid, dim3(kThreads), 0, s, tab, g, tb);        \
+    break;
+    MBS_FOR_EACH_N(MBS_CASE)
+#undef MBS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_green_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
+                             hipStream_t s) {
+  const int WC = cols_per_tile_c(g.n[0]);
+  const int64_t blocks = (int64_t)g.S * g.n[1] * ((g.n[2] + WC - 1) / WC);
+  dim3 grid((unsigned)blocks, nslots);
+  switch (g.n[0]) {
+#define MBS_CASE(NN) \
+  case NN: hipLaunchKernelGGL(k_green<NN>, grid, dim3(kThreads), 0, s, tab, g, tb); break;
+    MBS_FOR_EACH_N(MBS_CASE)
+#undef MBS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_corr(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, int which,
+                       hipStream_t s) {
+  for (int d = 0; d < 3; ++d) {
+    if (g.a[d] == 0) continue;
+    const int64_t plane = d == 0 ? (int64_t)g.n[1] * g.n[2]
+                                 : (d == 1 ? (int64_t)g.n[0] * g.n[2] : (int64_t)g.n[0] * g.n[1]);
+    const int64_t lines = (int64_t)g.S * plane;
+    dim3 grid((unsigned)((lines + kThreads - 1) / kThreads), nslots);
+    switch (g.t) {
+#define MBS_T(TT) \
+  case TT: hipLaunchKernelGGL(k_corr<TT>, grid, dim3(kThreads), 0, s, tab, g, tb.C, d, which); break;
+      MBS_T(1) MBS_T(2) MBS_T(3) MBS_T(4) MBS_T(5) MBS_T(6) MBS_T(7) MBS_T(8)
+      MBS_T(9) MBS_T(10) MBS_T(11) MBS_T(12) MBS_T(13) MBS_T(14) MBS_T(15) MBS_T(16)
+#undef MBS_T
+      default:
+        return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_face(const SlotDesc* tab, int nslots, const Geo& g, hipStream_t s) {
+  dim3 grid((unsigned)face_blocks(g), nslots);
+  hipLaunchKernelGGL(k_face, grid, dim3(kThreads), 0, s, tab, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const SlotDesc* tab, int nslots, const Geo& g, int64_t n_main,
+                         int64_t n_face, hipStream_t s) {
+  (void)g;
+  hipLaunchKernelGGL(k_reduce, dim3(nslots), dim3(kThreads), 0, s, tab, n_main, n_face);
+  return hipGetLastError();
+}
+
+int64_t setup_blocks(const Geo& g) { return grid_1d(g.vox, 4096); }
+
+hipError_t launch_medium_stats(const float2* n, const Geo& g, double k0sq, const int32_t* width,
+                               double ramp_max, MediumStats* partials, int64_t nblocks,
+                               hipStream_t s) {
+  Int3 w{{width[0], width[1], width[2]}};
+  hipLaunchKernelGGL(k_medium_stats, dim3((unsigned)nblocks), dim3(kThreads), 0, s, n, g, k0sq, w,
+                     ramp_max, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_medium_kmax(const float2* n, const Geo& g, double k0sq, const int32_t* width,
+                              double ramp_max, double kb2, double* partials, int64_t nblocks,
+                              hipStream_t s) {
+  Int3 w{{width[0], width[1], width[2]}};
+  hipLaunchKernelGGL(k_medium_kmax, dim3((unsigned)nblocks), dim3(kThreads), 0, s, n, g, k0sq, w,
+                     ramp_max, kb2, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_medium_B(const float2* n, const Geo& g, double k0sq, const int32_t* width,
+                           double ramp_max, double kb2, double c_im, float2* B, hipStream_t s) {
+  Int3 w{{width[0], width[1], width[2]}};
+  hipLaunchKernelGGL(k_medium_B, dim3(grid_1d(g.vox)), dim3(kThreads), 0, s, n, g, k0sq, w, ramp_max,
+                     kb2, c_im, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_source_bbox(const float2* S, const Geo& g, int32_t* bbox, hipStream_t s) {
+  hipLaunchKernelGGL(k_source_bbox, dim3(grid_1d(g.vox)), dim3(kThreads), 0, s, S, g, bbox);
+  return hipGetLastError();
+}
+
+hipError_t launch_source_fill(const float2* S, const Geo& g, const int32_t* lo, const int32_t* ext,
+                              double c_im, float2* ybox, hipStream_t s) {
+  Int3 l{{lo[0], lo[1], lo[2]}}, e{{ext[0], ext[1], ext[2]}};
+  const int64_t nb = (int64_t)ext[0] * ext[1] * ext[2];
+  hipLaunchKernelGGL(k_source_fill, dim3(grid_1d(nb)), dim3(kThreads), 0, s, S, g, l, e, c_im, ybox);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const float2* field, const Geo& g, float2* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, dim3(grid_1d(g.vox)), dim3(kThreads), 0, s, field, g, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const float2* x, const Geo& g, float2* field, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, dim3(grid_1d(g.vox)), dim3(kThreads), 0, s, x, g, field);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(float2* p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero, dim3(grid_1d(n)), dim3(kThreads), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_slabs(const SlotDesc* tab, int slot, const Geo& g, int which,
+                                hipStream_t s) {
+  (void)which;
+  for (int d = 0; d < 3; ++d) {
+    if (g.a[d] == 0) continue;
+    const int64_t plane = d == 0 ? (int64_t)g.n[1] * g.n[2]
+                                 : (d == 1 ? (int64_t)g.n[0] * g.n[2] : (int64_t)g.n[0] * g.n[1]);
+    const int64_t total = (int64_t)g.S * 2 * g.t * plane;
+    hipLaunchKernelGGL(k_extract, dim3(grid_1d(total)), dim3(kThreads), 0, s, tab, slot, g, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace mbs

@@ -1,0 +1,184 @@
+"""GPU path vs the FP64 oracle, element by element, through the C ABI.
+
+The bar (relative L2 <= 2e-5 at a fixed iteration count) compares complex64
+FFT/pointwise arithmetic with FP64 residual reductions against an all-FP64
+reference on identical inputs.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from _mbs_cases import gpu_solve, oracle_problem, random_case, rel_l2, workload, workload_inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-5
+
+
+def _compare(shape, split, periodic, t, n, S, k_vac, rw, rm, iters, tol_bar=TOL):
+    x_gpu, res, hist = gpu_solve(shape, split, periodic, t, n, S, k_vac, rw, rm, 0.0, iters)
+    pr = oracle_problem(shape, split, periodic, t, n, k_vac, rw, rm)
+    ref = pr.solve(S, tol=0.0, max_iter=iters)
+    print(f"shape={shape} split={split} periodic={periodic} t={t} iters={iters}", flush=True)
+    assert res["iterations"] == iters
+    # FP64 scalars agree with the oracle's own
+    assert abs(res["kb2"] - pr.kb2) <= 1e-12 * abs(pr.kb2)
+    assert abs(res["K"] - pr.K) <= 1e-12 * pr.K
+    assert abs(res["c_imag"] - pr.c.imag) <= 1e-12 * abs(pr.c.imag)
+    assert abs(res["normC"] - pr.normC) <= 1e-12 * pr.normC
+    err = rel_l2(x_gpu, ref.x)
+    print(f"  rel L2 vs oracle = {err:.3e}", flush=True)
+    assert err <= tol_bar, err
+    # per-iteration relative residuals agree too
+    h = np.asarray(hist)
+    e = np.asarray(ref.eps)
+    assert np.max(np.abs(h - e) / e) < 1e-3
+    return err
+
+
+def test_plain_sphere_64_fixed_iterations():
+    w = workload("plain64")
+    n, S = workload_inputs(w)
+    _compare(w.shape, w.split, w.periodic, w.t, n, S, w.k_vac, w.ramp_width, w.ramp_max, 100)
+
+
+def test_plain_sphere_64_to_tolerance():
+    """Run the oracle to 1e-6 and the GPU to its FP32 residual floor: the GPU
+    field agrees with the converged FP64 field, and the GPU stops at 1e-5."""
+    w = workload("plain64")
+    n, S = workload_inputs(w)
+    x_gpu, res, hist = gpu_solve(w.shape, w.split, w.periodic, w.t, n, S, w.k_vac, w.ramp_width,
+                                 w.ramp_max, 1e-5, 5000)
+    pr = oracle_problem(w.shape, w.split, w.periodic, w.t, n, w.k_vac, w.ramp_width, w.ramp_max)
+    ref = pr.solve(S, tol=1e-6, max_iter=5000)
+    err = rel_l2(x_gpu, ref.x)
+    h = np.asarray(hist)
+    print(f"plain64: gpu {res['iterations']} it to {res['rel_residual']:.2e}, oracle {ref.iterations} it "
+          f"to 1e-6, rel L2 {err:.3e}; ||x||/rho_ref = {np.linalg.norm(x_gpu) / res['rho_ref']:.1f}; "
+          f"gpu eps tail {h[-5:]}", flush=True)
+    assert res["converged"] == 1 and ref.converged
+    assert err <= 5e-5
+    # oracle's own relative residual of the GPU field
+    ro = pr.relative_residual(x_gpu.astype(np.complex128), S)
+    print(f"  oracle residual of the GPU field: {ro:.3e}", flush=True)
+    assert ro < 2e-5
+    # the library's residual evaluation of a given field agrees with the oracle's
+    import torch
+    from paper_2410_02395_amd import mbs
+    dev = torch.device("cuda:0")
+    with mbs.Plan(w.shape, w.split, w.periodic, w.t) as plan:
+        plan.set_medium(0, torch.from_numpy(n).to(dev), w.k_vac, w.ramp_width, w.ramp_max)
+        _, r2 = plan.solve(0, torch.from_numpy(S).to(dev), 1e-3, 5000)
+        rr_last = plan.residual(0)
+        rr = plan.residual(0, torch.from_numpy(x_gpu).to(dev))
+        print(f"  library residual of the GPU field {rr:.3e}, of its own 1e-3 iterate {rr_last:.3e} "
+              f"(solve reported {r2['rel_residual']:.3e})", flush=True)
+        assert abs(rr - ro) <= 0.2 * ro + 2e-6
+        assert rr_last < 1.2e-3
+
+
+@pytest.mark.parametrize("shape,split,periodic,t", [
+    ((64, 64, 64), (2, 2, 2), (0, 0, 0), 8),     # 8 subdomains of 32^3, wrap removal everywhere
+    ((48, 24, 96), (2, 1, 2), (1, 0, 0), 4),     # ragged tiles, cyclic split axis, radix 3
+    ((32, 64, 16), (1, 2, 1), (0, 1, 1), 4),     # periodic split axis, mixed a_d
+    ((24, 16, 12), (3, 2, 1), (0, 0, 0), 2),     # three subdomains along x, tiny edges
+])
+def test_decomposed_fixed_iterations(shape, split, periodic, t):
+    n, S = random_case(shape, seed=7)
+    k = 2 * math.pi / 4
+    _compare(shape, split, periodic, t, n, S, k, (4, 4, 4), 0.2, 60)
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (16, 12, 24), (96, 32, 64), (12, 192, 8)])
+def test_plain_sizes_and_radices(shape):
+    n, S = random_case(shape, seed=3, src="plane")
+    _compare(shape, (1, 1, 1), (1, 1, 1), 8, n, S, 2 * math.pi / 5, (2, 2, 2), 0.3, 40)
+
+
+def test_zero_source_gives_zero_field():
+    shape = (32, 32, 32)
+    n, _ = random_case(shape)
+    x, res, _ = gpu_solve(shape, (1, 1, 1), (1, 1, 1), 8, n, np.zeros(shape, np.complex64),
+                          1.0, (4, 4, 4), 0.2, 1e-6, 100)
+    assert res["iterations"] == 1 and res["converged"] == 1
+    assert np.all(x == 0)
+
+
+def test_resume_from_checkpoint_is_bitwise():
+    """Richardson is memoryless: k iterations, then k more from x_k, equals 2k iterations."""
+    from paper_2410_02395_amd import mbs
+    shape, split, periodic = (32, 32, 32), (2, 1, 1), (0, 1, 1)
+    n, S = random_case(shape, seed=11)
+    k = 2 * math.pi / 4
+    full, _, _ = gpu_solve(shape, split, periodic, 4, n, S, k, (4, 4, 4), 0.2, 0.0, 40)
+    half, _, _ = gpu_solve(shape, split, periodic, 4, n, S, k, (4, 4, 4), 0.2, 0.0, 20)
+    rest, res, _ = gpu_solve(shape, split, periodic, 4, n, S, k, (4, 4, 4), 0.2, 0.0, 20,
+                             flags=mbs.MBS_X0_GIVEN, x0=half)
+    assert np.array_equal(rest, full)
+
+
+def test_graph_and_eager_launches_agree_bitwise():
+    from paper_2410_02395_amd import mbs
+    shape, split, periodic = (32, 32, 32), (2, 2, 1), (0, 0, 1)
+    n, S = random_case(shape, seed=5)
+    k = 2 * math.pi / 4
+    a, ra, _ = gpu_solve(shape, split, periodic, 4, n, S, k, (4, 4, 4), 0.2, 0.0, 37, check_every=8)
+    b, rb, _ = gpu_solve(shape, split, periodic, 4, n, S, k, (4, 4, 4), 0.2, 0.0, 37,
+                         flags=mbs.MBS_NO_GRAPH)
+    c, rc, _ = gpu_solve(shape, split, periodic, 4, n, S, k, (4, 4, 4), 0.2, 0.0, 37,
+                         flags=mbs.MBS_TIMING, check_every=5)
+    assert ra["iterations"] == rb["iterations"] == rc["iterations"] == 37
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_residual_history_is_monotone():
+    w = workload("plain64")
+    n, S = workload_inputs(w)
+    _, res, hist = gpu_solve(w.shape, w.split, w.periodic, w.t, n, S, w.k_vac, w.ramp_width,
+                             w.ramp_max, 1e-5, 3000)
+    h = np.asarray(hist)
+    assert len(h) == res["iterations"]
+    assert np.all(h[1:] <= h[:-1] * (1 + 1e-4))
+
+
+def test_error_paths():
+    import torch
+    from paper_2410_02395_amd import mbs
+    dev = torch.device("cuda:0")
+    shape = (16, 16, 16)
+    ones = torch.ones(shape, dtype=torch.complex64, device=dev)
+    S = torch.zeros(shape, dtype=torch.complex64, device=dev)
+    S[3, 3, 3] = 1
+    with pytest.raises(mbs.MBSError) as e:
+        mbs.Plan((100, 16, 16))
+    assert e.value.status == mbs.MBS_EUNSUPPORTED
+    with pytest.raises(mbs.MBSError) as e:
+        mbs.Plan(shape, (2, 1, 1), (0, 0, 0), t=5)   # t > n/2
+    assert e.value.status == mbs.MBS_EINVAL
+    with mbs.Plan(shape) as plan:
+        with pytest.raises(mbs.MBSError) as e:
+            plan.solve(0, S, 1e-6, 10)
+        assert e.value.status == mbs.MBS_ESTATE
+        with pytest.raises(mbs.MBSError) as e:
+            plan.set_medium(0, ones, 1.0)           # lossless homogeneous periodic: K = 0
+        assert e.value.status == mbs.MBS_EDEGENERATE
+        gain = ones.clone()
+        gain[1, 2, 3] = 1.0 - 0.2j
+        with pytest.raises(mbs.MBSError) as e:
+            plan.set_medium(0, gain, 1.0, (2, 2, 2), 0.1)
+        assert e.value.status == mbs.MBS_EGAIN
+        bad = ones.clone()
+        bad[0, 0, 0] = float("nan")
+        with pytest.raises(mbs.MBSError) as e:
+            plan.set_medium(0, bad, 1.0, (2, 2, 2), 0.1)
+        assert e.value.status == mbs.MBS_ENONFINITE
+        plan.set_medium(0, ones, 1.0, (2, 2, 2), 0.1)
+        badS = S.clone()
+        badS[1, 1, 1] = float("inf")
+        with pytest.raises(mbs.MBSError) as e:
+            plan.solve(0, badS, 1e-6, 10)
+        assert e.value.status == mbs.MBS_ENONFINITE
+        _, r = plan.solve(0, S, 1e-12, 3)          # not converging is not an error
+        assert r["iterations"] == 3 and r["converged"] == 0
