@@ -54,7 +54,8 @@ __all__ = [
     "dense_laplacian", "dense_solve", "spectral_solve_homogeneous",
 ]
 
-WORKERS = int(os.environ.get("MBS_ORACLE_THREADS", os.cpu_count() or 1))
+WORKERS = int(os.environ.get("MBS_ORACLE_THREADS",
+                             os.environ.get("OMP_NUM_THREADS", min(16, os.cpu_count() or 1))))
 
 
 # --------------------------------------------------------------------------

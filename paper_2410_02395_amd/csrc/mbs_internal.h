@@ -9,6 +9,7 @@ namespace mbs {
 constexpr int kThreads = 256;       // threads per workgroup of every kernel (4 wavefronts)
 constexpr int kMaxT = 16;           // largest truncation t of the correction blocks
 constexpr int kHistCap = 1 << 16;   // residual history entries kept per slot
+constexpr int kReduceBlocks = 64;   // first-stage workgroups of the residual reduction
 
 // stop reasons written by the residual kernel
 enum : int32_t {
@@ -50,6 +51,8 @@ struct Geo {
   int32_t reg_ext[3][3]; // extents of region d along each axis
   int32_t reg_off[3][3]; // offsets of region d along each axis (axis d itself: slab code)
   int64_t face_vox;      // sum of reg_count (per subdomain)
+  int32_t cus;           // compute units of the device (persistent grid size)
+  int32_t pad;
 };
 
 // Per-slot pointers and scalars, in device memory (one table entry per slot).
@@ -70,6 +73,7 @@ struct SlotDesc {
   double* part_main;      // residual partials of the last inverse pass
   double* part_face;      // residual partials of the face update
   double* hist;           // relative residual per iteration
+  double* part_red;       // first-stage sums of the residual reduction (kReduceBlocks)
   int32_t active;
   int32_t pad;
 };

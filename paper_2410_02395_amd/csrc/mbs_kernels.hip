@@ -117,6 +117,32 @@ struct Bfly<SIGN, 8> {
 __host__ __device__ constexpr int radix_of(int rem) {
   return rem % 3 == 0 ? 3 : (rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : 2));
 }
+__host__ __device__ constexpr int plan_len(int n) {
+  int c = 0;
+  while (n > 1) {
+    n /= radix_of(n);
+    ++c;
+  }
+  return c;
+}
+__host__ __device__ constexpr int radix_at(int n, int s) {
+  for (int k = 0; k < s; ++k) n /= radix_of(n);
+  return radix_of(n);
+}
+// radix of stage s of the forward (rev = false) or reversed (rev = true) radix sequence
+__host__ __device__ constexpr int plan_radix(int n, int s, bool rev) {
+  return radix_at(n, rev ? plan_len(n) - 1 - s : s);
+}
+// product of the radices before stage s (the length of the sub-transforms already done)
+__host__ __device__ constexpr int plan_ns(int n, int s, bool rev) {
+  int p = 1;
+  for (int k = 0; k < s; ++k) p *= plan_radix(n, k, rev);
+  return p;
+}
+
+// barrier for LDS traffic only: waits for this wave's LDS operations, not for its
+// outstanding global loads, so prefetches stay in flight across FFT stages
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // ---------------------------------------------------------------------------
 // tile layouts in LDS
@@ -130,6 +156,7 @@ __host__ __device__ constexpr int cols_per_tile_c(int n) {
 // slot every 16 to spread the stride-R writes of the first stage over the banks.
 template <int N, int LINES>
 struct LineTile {
+  static constexpr int NT = kThreads;
   static constexpr int ELEMS = N * LINES;
   static constexpr int LDS = ELEMS + ELEMS / 16 + 1;
   __device__ __forceinline__ static int idx(int j, int l) {
@@ -145,9 +172,20 @@ struct LineTile {
   static constexpr int nb() { return (N / R) * LINES; }
 };
 
+__host__ __device__ constexpr int col_threads_c(int n) { return n >= 384 ? 512 : kThreads; }
+// minimum waves per SIMD requested for the column tiles (register budget per thread)
+#ifndef MBS_COL_WAVES_BIG
+#define MBS_COL_WAVES_BIG 2
+#endif
+#ifndef MBS_COL_PREFETCH
+#define MBS_COL_PREFETCH 1
+#endif
+__host__ __device__ constexpr int col_waves_c(int n) { return col_threads_c(n) == 512 ? MBS_COL_WAVES_BIG : 2; }
+
 // N rows (the FFT axis) x WC contiguous columns; element (j, c) at j*WC + c.
 template <int N, int WC>
 struct ColTile {
+  static constexpr int NT = col_threads_c(N);
   static constexpr int ELEMS = N * WC;
   static constexpr int LDS = ELEMS;
   __device__ __forceinline__ static int idx(int j, int c) { return j * WC + c; }
@@ -160,57 +198,105 @@ struct ColTile {
   static constexpr int nb() { return (N / R) * WC; }
 };
 
-// One radix-R Stockham stage in place in LDS (read all, barrier, write all, barrier).
-// Butterfly i (of N/R per line) reads elements i + m N/R, multiplies input m by
-// w^(m k) (k = i mod NS, w = exp(SIGN 2 pi i / (NS R))), and writes output m to
-// (i - k) R + k + m NS.
-template <class Tile, int N, int R, int NS, int SIGN>
-__device__ __forceinline__ void stockham_stage(float2* lds, const float2* __restrict__ tw, int tid) {
+// butterflies per thread in a stage of radix R
+template <class Tile, int R>
+__host__ __device__ constexpr int per_thread() { return (Tile::template nb<R>() + Tile::NT - 1) / Tile::NT; }
+
+template <class Tile, int R>
+__device__ __forceinline__ bool bvalid(int q, int tid) {
   constexpr int NB = Tile::template nb<R>();
-  constexpr int PER = (NB + kThreads - 1) / kThreads;
-  constexpr int STRIDE = N / R;
-  float2 v[PER][R];
-  int ob[PER], lb[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int b = tid + q * kThreads;
-    if ((NB % kThreads) == 0 || b < NB) {
-      int i, l;
-      Tile::template bf<R>(b, i, l);
-      const int k = i % NS;
-#pragma unroll
-      for (int m = 0; m < R; ++m) v[q][m] = lds[Tile::idx(i + m * STRIDE, l)];
-      if constexpr (NS > 1) {
-#pragma unroll
-        for (int m = 1; m < R; ++m) {
-          float2 w = tw[(m * k) * (N / (NS * R))];
-          if (SIGN > 0) w.y = -w.y;
-          v[q][m] = cmul(v[q][m], w);
-        }
-      }
-      Bfly<SIGN, R>::run(v[q]);
-      ob[q] = (i - k) * R + k;
-      lb[q] = l;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int b = tid + q * kThreads;
-    if ((NB % kThreads) == 0 || b < NB) {
-#pragma unroll
-      for (int m = 0; m < R; ++m) lds[Tile::idx(ob[q] + m * NS, lb[q])] = v[q][m];
-    }
-  }
-  __syncthreads();
+  return (NB % Tile::NT) == 0 || tid + q * Tile::NT < NB;
 }
 
-template <class Tile, int N, int NS, int SIGN>
-__device__ __forceinline__ void fft_stages(float2* lds, const float2* __restrict__ tw, int tid) {
-  if constexpr (NS < N) {
-    constexpr int R = radix_of(N / NS);
-    stockham_stage<Tile, N, R, NS, SIGN>(lds, tw, tid);
-    fft_stages<Tile, N, NS * R, SIGN>(lds, tw, tid);
+// Stockham stage (radix R, NS = length of the sub-transforms already done): butterfly i
+// (of N/R per line) takes elements i + m N/R, multiplies input m by w^(m k) with
+// k = i mod NS and w = exp(SIGN 2 pi i / (NS R)), and produces outputs at
+// (i - k) R + k + m NS.  The data of butterfly q of this thread is v[q][0..R).
+template <class Tile, int N, int R, int NS, int SIGN, int PER>
+__device__ __forceinline__ void bfly_regs(float2 (&v)[PER][R], const float2* __restrict__ tw, int tid) {
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if (!bvalid<Tile, R>(q, tid)) continue;
+    if constexpr (NS > 1) {
+      int i, l;
+      Tile::template bf<R>(tid + q * Tile::NT, i, l);
+      const int k = i % NS;
+#pragma unroll
+      for (int m = 1; m < R; ++m) {
+        float2 w = tw[(m * k) * (N / (NS * R))];
+        if (SIGN > 0) w.y = -w.y;
+        v[q][m] = cmul(v[q][m], w);
+      }
+    }
+    Bfly<SIGN, R>::run(v[q]);
+  }
+}
+
+template <class Tile, int N, int R, int NS, int PER>
+__device__ __forceinline__ void put_lds(float2* lds, const float2 (&v)[PER][R], int tid) {
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if (!bvalid<Tile, R>(q, tid)) continue;
+    int i, l;
+    Tile::template bf<R>(tid + q * Tile::NT, i, l);
+    const int k = i % NS;
+    const int o = (i - k) * R + k;
+#pragma unroll
+    for (int m = 0; m < R; ++m) lds[Tile::idx(o + m * NS, l)] = v[q][m];
+  }
+}
+
+template <class Tile, int N, int R, int PER>
+__device__ __forceinline__ void get_lds(const float2* lds, float2 (&v)[PER][R], int tid) {
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if (!bvalid<Tile, R>(q, tid)) continue;
+    int i, l;
+    Tile::template bf<R>(tid + q * Tile::NT, i, l);
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[q][m] = lds[Tile::idx(i + m * (N / R), l)];
+  }
+}
+
+// stages S .. SEND-1 of the plan, in place in LDS
+template <class Tile, int N, bool REV, int SIGN, int S, int SEND>
+__device__ __forceinline__ void lds_stages(float2* lds, const float2* __restrict__ tw, int tid) {
+  if constexpr (S < SEND) {
+    constexpr int R = plan_radix(N, S, REV);
+    constexpr int NS = plan_ns(N, S, REV);
+    constexpr int PER = per_thread<Tile, R>();
+    float2 v[PER][R];
+    get_lds<Tile, N, R, PER>(lds, v, tid);
+    bfly_regs<Tile, N, R, NS, SIGN, PER>(v, tw, tid);
+    lds_barrier();
+    put_lds<Tile, N, R, NS, PER>(lds, v, tid);
+    lds_barrier();
+    lds_stages<Tile, N, REV, SIGN, S + 1, SEND>(lds, tw, tid);
+  }
+}
+
+// Whole FFT of a tile.  `in` holds the inputs of stage 0 (elements i + m N/R0 of this
+// thread's butterflies), `out` receives the outputs of the last stage (elements
+// i + m N/RL, natural order).  Starts with a barrier, so the caller may have been
+// reading LDS just before.
+template <class Tile, int N, bool REV, int SIGN, int PER0, int R0, int PERL, int RL>
+__device__ __forceinline__ void fft_tile(float2 (&in)[PER0][R0], float2 (&out)[PERL][RL], float2* lds,
+                                         const float2* __restrict__ tw, int tid) {
+  constexpr int P = plan_len(N);
+  static_assert(R0 == plan_radix(N, 0, REV) && RL == plan_radix(N, P - 1, REV), "plan mismatch");
+  bfly_regs<Tile, N, R0, 1, SIGN, PER0>(in, tw, tid);
+  if constexpr (P == 1) {
+#pragma unroll
+    for (int q = 0; q < PER0; ++q)
+#pragma unroll
+      for (int m = 0; m < R0; ++m) out[q][m] = in[q][m];
+  } else {
+    lds_barrier();
+    put_lds<Tile, N, R0, 1, PER0>(lds, in, tid);
+    lds_barrier();
+    lds_stages<Tile, N, REV, SIGN, 1, P - 1>(lds, tw, tid);
+    get_lds<Tile, N, RL, PERL>(lds, out, tid);
+    bfly_regs<Tile, N, RL, plan_ns(N, P - 1, REV), SIGN, PERL>(out, tw, tid);
   }
 }
 
@@ -305,6 +391,9 @@ __global__ __launch_bounds__(kThreads) void k_first(const SlotDesc* __restrict__
   if (sd.st->done != kRunning) return;
   constexpr int L = lines_per_wg_c(N);
   using Tile = LineTile<N, L>;
+  constexpr int P = plan_len(N);
+  constexpr int R0 = plan_radix(N, 0, false), RL = plan_radix(N, P - 1, false);
+  constexpr int PER0 = per_thread<Tile, R0>(), PERL = per_thread<Tile, RL>();
   __shared__ float2 lds[Tile::LDS];
   __shared__ LineInfo info[L];
   const int tid = threadIdx.x;
@@ -313,30 +402,41 @@ __global__ __launch_bounds__(kThreads) void k_first(const SlotDesc* __restrict__
   __syncthreads();
   const int t = g.t;
   const int64_t plane2 = (int64_t)g.n[0] * g.n[1];
-  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
-    const int l = f / N;
-    const int j = f - l * N;
-    const LineInfo& li = info[l];
-    float2 w = make_float2(0.f, 0.f);
-    if (li.valid) {
-      const int64_t gi = li.gbase + j;
-      w = cmul(sd.B[gi], sd.x[gi]);
-      if (li.e0 >= 0) w = cadd(w, sd.slab[0][2][li.e0 + j]);
-      if (li.e1 >= 0) w = cadd(w, sd.slab[1][2][li.e1 + j]);
-      if (li.e2 >= 0) {
-        if (j < t) w = cadd(w, sd.slab[2][2][li.e2 + (int64_t)j * plane2]);
-        else if (j >= N - t) w = cadd(w, sd.slab[2][2][li.e2 + (int64_t)(t + j - (N - t)) * plane2]);
+  float2 v[PER0][R0];
+#pragma unroll
+  for (int q = 0; q < PER0; ++q) {
+    int i = 0, l = 0;
+    const bool ok = bvalid<Tile, R0>(q, tid);
+    if (ok) Tile::template bf<R0>(tid + q * kThreads, i, l);
+    const LineInfo& li = info[ok ? l : 0];
+#pragma unroll
+    for (int m = 0; m < R0; ++m) {
+      const int j = i + m * (N / R0);
+      float2 w = make_float2(0.f, 0.f);
+      if (ok && li.valid) {
+        const int64_t gi = li.gbase + j;
+        w = cmul(sd.B[gi], sd.x[gi]);
+        if (li.e0 >= 0) w = cadd(w, sd.slab[0][2][li.e0 + j]);
+        if (li.e1 >= 0) w = cadd(w, sd.slab[1][2][li.e1 + j]);
+        if (li.e2 >= 0) {
+          if (j < t) w = cadd(w, sd.slab[2][2][li.e2 + (int64_t)j * plane2]);
+          else if (j >= N - t) w = cadd(w, sd.slab[2][2][li.e2 + (int64_t)(t + j - (N - t)) * plane2]);
+        }
+        if (j >= li.jlo && j < li.jhi) w = cadd(w, sd.ybox[li.ybase + j]);
       }
-      if (j >= li.jlo && j < li.jhi) w = cadd(w, sd.ybox[li.ybase + j]);
+      v[q][m] = w;
     }
-    lds[Tile::idx(j, l)] = w;
   }
-  __syncthreads();
-  fft_stages<Tile, N, 1, -1>(lds, tb.tw[2], tid);
-  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
-    const int l = f / N;
-    const int j = f - l * N;
-    if (info[l].valid) sd.W[info[l].gbase + j] = lds[Tile::idx(j, l)];
+  float2 o[PERL][RL];
+  fft_tile<Tile, N, false, -1>(v, o, lds, tb.tw[2], tid);
+#pragma unroll
+  for (int q = 0; q < PERL; ++q) {
+    if (!bvalid<Tile, RL>(q, tid)) continue;
+    int i, l;
+    Tile::template bf<RL>(tid + q * kThreads, i, l);
+    if (!info[l].valid) continue;
+#pragma unroll
+    for (int m = 0; m < RL; ++m) sd.W[info[l].gbase + i + m * (N / RL)] = o[q][m];
   }
 }
 
@@ -351,6 +451,9 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
   if (sd.st->done != kRunning) return;
   constexpr int L = lines_per_wg_c(N);
   using Tile = LineTile<N, L>;
+  constexpr int P = plan_len(N);
+  constexpr int R0 = plan_radix(N, 0, false), RL = plan_radix(N, P - 1, false);
+  constexpr int PER0 = per_thread<Tile, R0>(), PERL = per_thread<Tile, RL>();
   __shared__ float2 lds[Tile::LDS];
   __shared__ LineInfo info[L];
   __shared__ double red[kThreads / 64];
@@ -358,125 +461,173 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
   const int64_t line0 = (int64_t)blockIdx.x * L;
   for (int l = tid; l < L; l += kThreads) line_info(line0 + l, g, sd, info[l]);
   __syncthreads();
-  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
-    const int l = f / N;
-    const int j = f - l * N;
-    lds[Tile::idx(j, l)] = info[l].valid ? sd.W[info[l].gbase + j] : make_float2(0.f, 0.f);
+  float2 v[PER0][R0];
+#pragma unroll
+  for (int q = 0; q < PER0; ++q) {
+    int i = 0, l = 0;
+    const bool ok = bvalid<Tile, R0>(q, tid);
+    if (ok) Tile::template bf<R0>(tid + q * kThreads, i, l);
+    const LineInfo& li = info[ok ? l : 0];
+#pragma unroll
+    for (int m = 0; m < R0; ++m)
+      v[q][m] = (ok && li.valid) ? sd.W[li.gbase + i + m * (N / R0)] : make_float2(0.f, 0.f);
   }
-  __syncthreads();
-  fft_stages<Tile, N, 1, +1>(lds, tb.tw[2], tid);
+  float2 o[PERL][RL];
+  fft_tile<Tile, N, false, +1>(v, o, lds, tb.tw[2], tid);
   const int t = g.t;
   const int64_t plane2 = (int64_t)g.n[0] * g.n[1];
   const float alpha = sd.alpha;
   double acc = 0.0;
-  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
-    const int l = f / N;
-    const int j = f - l * N;
+#pragma unroll
+  for (int q = 0; q < PERL; ++q) {
+    if (!bvalid<Tile, RL>(q, tid)) continue;
+    int i, l;
+    Tile::template bf<RL>(tid + q * kThreads, i, l);
     const LineInfo& li = info[l];
     if (!li.valid) continue;
-    const int64_t gi = li.gbase + j;
-    const float2 v = lds[Tile::idx(j, l)];
-    const float2 xv = sd.x[gi];
-    const float2 u = csub(xv, v);
-    const float2 bu = cmul(sd.B[gi], u);
-    sd.x[gi] = make_float2(xv.x - alpha * bu.x, xv.y - alpha * bu.y);
-    bool edge = false;
-    if (li.e0 >= 0) { sd.slab[0][1][li.e0 + j] = u; edge = true; }
-    if (li.e1 >= 0) { sd.slab[1][1][li.e1 + j] = u; edge = true; }
-    if (li.e2 >= 0) {
-      if (j < t) { sd.slab[2][1][li.e2 + (int64_t)j * plane2] = u; edge = true; }
-      else if (j >= N - t) { sd.slab[2][1][li.e2 + (int64_t)(t + j - (N - t)) * plane2] = u; edge = true; }
+#pragma unroll
+    for (int m = 0; m < RL; ++m) {
+      const int j = i + m * (N / RL);
+      const int64_t gi = li.gbase + j;
+      const float2 xv = sd.x[gi];
+      const float2 u = csub(xv, o[q][m]);
+      const float2 bu = cmul(sd.B[gi], u);
+      sd.x[gi] = make_float2(xv.x - alpha * bu.x, xv.y - alpha * bu.y);
+      bool edge = false;
+      if (li.e0 >= 0) { sd.slab[0][1][li.e0 + j] = u; edge = true; }
+      if (li.e1 >= 0) { sd.slab[1][1][li.e1 + j] = u; edge = true; }
+      if (li.e2 >= 0) {
+        if (j < t) { sd.slab[2][1][li.e2 + (int64_t)j * plane2] = u; edge = true; }
+        else if (j >= N - t) { sd.slab[2][1][li.e2 + (int64_t)(t + j - (N - t)) * plane2] = u; edge = true; }
+      }
+      if (!edge) acc += (double)bu.x * bu.x + (double)bu.y * bu.y;
     }
-    if (!edge) acc += (double)bu.x * bu.x + (double)bu.y * bu.y;
   }
   const double s = block_sum(acc, red);
   if (tid == 0) sd.part_main[blockIdx.x] = s;
 }
 
 // ---------------------------------------------------------------------------
-// strided passes: FFT along y (mid) or x (green, with the (L+I)^-1 symbol)
+// strided passes over N x WC column tiles: FFT along y (KIND 0 forward, 1 inverse)
+// or along x with the (L+I)^-1 symbol between the forward and inverse FFTs (KIND 2).
+// Persistent workgroups walk the tiles; the loads of the next tile are issued
+// before the LDS stages of the current one so that HBM traffic and LDS work overlap.
 // ---------------------------------------------------------------------------
-template <int N, int SIGN>
-__global__ __launch_bounds__(kThreads) void k_mid(const SlotDesc* __restrict__ tab, Geo g, Tables tb) {
-  const SlotDesc sd = tab[blockIdx.y];
-  if (sd.st->done != kRunning) return;
-  constexpr int WC = cols_per_tile_c(N);
+template <int N, int WC, int R, int PER>
+__device__ __forceinline__ void load_cols(float2 (&v)[PER][R], const float2* __restrict__ W, int64_t base,
+                                          int64_t stride, int ncols, int tid) {
   using Tile = ColTile<N, WC>;
-  __shared__ float2 lds[Tile::LDS];
-  const int tid = threadIdx.x;
-  const int n0 = g.n[0], n2 = g.n[2];
-  const int CB = (n2 + WC - 1) / WC;
-  const int cb = blockIdx.x % CB;
-  const int64_t rest = blockIdx.x / CB;
-  const int i0 = (int)(rest % n0);
-  const int s = (int)(rest / n0);
-  const int c0 = cb * WC;
-  const int ncols = min(WC, n2 - c0);
-  const int64_t base = (((int64_t)s * n0 + i0) * N) * n2 + c0;
-  const int64_t stride = n2;
-  float2* __restrict__ W = sd.W;
-  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
-    const int c = f % WC;
-    const int j = f / WC;
-    lds[Tile::idx(j, c)] = c < ncols ? W[base + j * stride + c] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  fft_stages<Tile, N, 1, SIGN>(lds, tb.tw[1], tid);
-  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
-    const int c = f % WC;
-    const int j = f / WC;
-    if (c < ncols) W[base + j * stride + c] = lds[Tile::idx(j, c)];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const bool ok = bvalid<Tile, R>(q, tid);
+    int i = 0, c = 0;
+    if (ok) Tile::template bf<R>(tid + q * Tile::NT, i, c);
+#pragma unroll
+    for (int m = 0; m < R; ++m)
+      v[q][m] = (ok && c < ncols) ? W[base + (int64_t)(i + m * (N / R)) * stride + c] : make_float2(0.f, 0.f);
   }
 }
 
-template <int N>
-__global__ __launch_bounds__(kThreads) void k_green(const SlotDesc* __restrict__ tab, Geo g, Tables tb) {
-  const SlotDesc sd = tab[blockIdx.y];
+template <int N, int KIND>
+__global__ __launch_bounds__(col_threads_c(N), col_waves_c(N)) void k_col(const SlotDesc* __restrict__ tab, Geo g, Tables tb,
+                                                      int64_t ntiles) {
+  const SlotDesc& sd = tab[blockIdx.y];
   if (sd.st->done != kRunning) return;
+  int64_t tile = blockIdx.x;
+  if (tile >= ntiles) return;
   constexpr int WC = cols_per_tile_c(N);
   using Tile = ColTile<N, WC>;
+  constexpr int P = plan_len(N);
+  constexpr int R0 = plan_radix(N, 0, false), RL = plan_radix(N, P - 1, false);
+  constexpr int PER0 = per_thread<Tile, R0>(), PERL = per_thread<Tile, RL>();
   __shared__ float2 lds[Tile::LDS];
   const int tid = threadIdx.x;
-  const int n1 = g.n[1], n2 = g.n[2];
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
   const int CB = (n2 + WC - 1) / WC;
-  const int cb = blockIdx.x % CB;
-  const int64_t rest = blockIdx.x / CB;
-  const int i1 = (int)(rest % n1);
-  const int s = (int)(rest / n1);
-  const int c0 = cb * WC;
-  const int ncols = min(WC, n2 - c0);
-  const int64_t base = ((int64_t)s * N * n1 + i1) * n2 + c0;
-  const int64_t stride = (int64_t)n1 * n2;
+  const int nfix = KIND == 2 ? n1 : n0;   // the tile's fixed coordinate runs over y (x pass) or x (y pass)
+  const int64_t stride = KIND == 2 ? (int64_t)n1 * n2 : (int64_t)n2;
   float2* __restrict__ W = sd.W;
-  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
-    const int c = f % WC;
-    const int j = f / WC;
-    lds[Tile::idx(j, c)] = c < ncols ? W[base + j * stride + c] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  fft_stages<Tile, N, 1, -1>(lds, tb.tw[0], tid);
-  // (L + I)^-1 = 1 / (1 + c (k_b^2 - |p|^2)), c = i c_im, with the 1/(n0 n1 n2) of the inverse
-  {
-    const float p21 = tb.p2[1][i1];
-    const float kb2 = sd.kb2, cim = sd.c_im, inv = sd.inv_vox;
-    for (int f = tid; f < Tile::ELEMS; f += kThreads) {
-      const int c = f % WC;
-      const int j = f / WC;
-      const int cz = c < ncols ? c0 + c : 0;
-      const float P = tb.p2[0][j] + p21 + tb.p2[2][cz];
-      const float E = cim * (kb2 - P);
-      const float den = inv / (1.f + E * E);
-      const float2 G = make_float2(den, -E * den);
-      const int ix = Tile::idx(j, c);
-      lds[ix] = cmul(lds[ix], G);
+  const float kb2 = sd.kb2, cim = sd.c_im, inv = sd.inv_vox;
+  auto locate = [&](int64_t tl, int& c0, int& ncols, int& fix) -> int64_t {
+    const int cb = (int)(tl % CB);
+    const int64_t rest = tl / CB;
+    fix = (int)(rest % nfix);
+    const int s = (int)(rest / nfix);
+    c0 = cb * WC;
+    ncols = min(WC, n2 - c0);
+    return KIND == 2 ? ((int64_t)s * N * n1 + fix) * n2 + c0 : (((int64_t)s * n0 + fix) * N) * n2 + c0;
+  };
+  int c0, ncols, fix;
+  int64_t base = locate(tile, c0, ncols, fix);
+  float2 cur[PER0][R0];
+  load_cols<N, WC, R0, PER0>(cur, W, base, stride, ncols, tid);
+  for (;;) {
+    const int64_t next = tile + gridDim.x;
+    const bool more = next < ntiles;
+    int nc0 = 0, nncols = 0, nfx = 0;
+    int64_t nbase = 0;
+    float2 nxt[PER0][R0];
+    if (MBS_COL_PREFETCH && more) {
+      nbase = locate(next, nc0, nncols, nfx);
+      load_cols<N, WC, R0, PER0>(nxt, W, nbase, stride, nncols, tid);
     }
-  }
-  __syncthreads();
-  fft_stages<Tile, N, 1, +1>(lds, tb.tw[0], tid);
-  for (int f = tid; f < Tile::ELEMS; f += kThreads) {
-    const int c = f % WC;
-    const int j = f / WC;
-    if (c < ncols) W[base + j * stride + c] = lds[Tile::idx(j, c)];
+    if constexpr (KIND == 2) {
+      float2 f[PERL][RL];
+      fft_tile<Tile, N, false, -1>(cur, f, lds, tb.tw[0], tid);
+      // (L + I)^-1 = 1 / (1 + c (k_b^2 - |p|^2)), c = i c_im, with the 1/(n0 n1 n2) of the inverse
+      const float p21 = tb.p2[1][fix];
+#pragma unroll
+      for (int q = 0; q < PERL; ++q) {
+        if (!bvalid<Tile, RL>(q, tid)) continue;
+        int i, c;
+        Tile::template bf<RL>(tid + q * Tile::NT, i, c);
+        const float p2z = tb.p2[2][c < ncols ? c0 + c : 0];
+#pragma unroll
+        for (int m = 0; m < RL; ++m) {
+          const float Pp = tb.p2[0][i + m * (N / RL)] + p21 + p2z;
+          const float E = cim * (kb2 - Pp);
+          const float den = inv / (1.f + E * E);
+          f[q][m] = cmul(f[q][m], make_float2(den, -E * den));
+        }
+      }
+      float2 o[PER0][R0];
+      fft_tile<Tile, N, true, +1>(f, o, lds, tb.tw[0], tid);
+#pragma unroll
+      for (int q = 0; q < PER0; ++q) {
+        if (!bvalid<Tile, R0>(q, tid)) continue;
+        int i, c;
+        Tile::template bf<R0>(tid + q * Tile::NT, i, c);
+        if (c >= ncols) continue;
+#pragma unroll
+        for (int m = 0; m < R0; ++m) W[base + (int64_t)(i + m * (N / R0)) * stride + c] = o[q][m];
+      }
+    } else {
+      float2 o[PERL][RL];
+      fft_tile<Tile, N, false, KIND == 1 ? +1 : -1>(cur, o, lds, tb.tw[1], tid);
+#pragma unroll
+      for (int q = 0; q < PERL; ++q) {
+        if (!bvalid<Tile, RL>(q, tid)) continue;
+        int i, c;
+        Tile::template bf<RL>(tid + q * Tile::NT, i, c);
+        if (c >= ncols) continue;
+#pragma unroll
+        for (int m = 0; m < RL; ++m) W[base + (int64_t)(i + m * (N / RL)) * stride + c] = o[q][m];
+      }
+    }
+    if (!more) break;
+    if (!MBS_COL_PREFETCH) {
+      nbase = locate(next, nc0, nncols, nfx);
+      load_cols<N, WC, R0, PER0>(nxt, W, nbase, stride, nncols, tid);
+    }
+#pragma unroll
+    for (int q = 0; q < PER0; ++q)
+#pragma unroll
+      for (int m = 0; m < R0; ++m) cur[q][m] = nxt[q][m];
+    tile = next;
+    base = nbase;
+    c0 = nc0;
+    ncols = nncols;
+    fix = nfx;
   }
 }
 
@@ -604,20 +755,35 @@ __global__ __launch_bounds__(kThreads) void k_face(const SlotDesc* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// residual norm, relative residual and stop test (one workgroup per slot)
+// residual norm in two fixed-order stages: kReduceBlocks workgroups sum contiguous
+// ranges of the partials, then one workgroup per slot sums those and applies the
+// relative residual and stop test (Sec. 3.1)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_reduce(const SlotDesc* __restrict__ tab, int64_t n_main,
-                                                     int64_t n_face) {
-  const SlotDesc sd = tab[blockIdx.x];
+__global__ __launch_bounds__(kThreads) void k_reduce1(const SlotDesc* __restrict__ tab, int64_t n_main,
+                                                      int64_t n_face) {
+  const SlotDesc& sd = tab[blockIdx.y];
+  if (sd.st->done != kRunning) return;
+  __shared__ double red[kThreads / 64];
+  const int64_t total = n_main + n_face;
+  const int64_t chunk = (total + kReduceBlocks - 1) / kReduceBlocks;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < total ? lo + chunk : total;
+  double acc = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads)
+    acc += i < n_main ? sd.part_main[i] : sd.part_face[i - n_main];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) sd.part_red[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(64) void k_reduce2(const SlotDesc* __restrict__ tab) {
+  const SlotDesc& sd = tab[blockIdx.x];
   SlotState* st = sd.st;
   if (st->done != kRunning) return;
-  __shared__ double red[kThreads / 64];
   double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n_main; i += kThreads) acc += sd.part_main[i];
-  for (int64_t i = threadIdx.x; i < n_face; i += kThreads) acc += sd.part_face[i];
-  const double tot = block_sum(acc, red);
+  for (int i = threadIdx.x; i < kReduceBlocks; i += 64) acc += sd.part_red[i];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (threadIdx.x != 0) return;
-  const double rho = sqrt(tot);
+  const double rho = sqrt(acc);
   st->rho = rho;
   if (st->probe) {
     st->done = isfinite(rho) ? kConverged : kNonFinite;
@@ -762,11 +928,13 @@ __global__ __launch_bounds__(kThreads) void k_medium_B(const float2* __restrict_
 
 __global__ __launch_bounds__(kThreads) void k_source_bbox(const float2* __restrict__ S, Geo g,
                                                           int32_t* bbox) {
+  __shared__ int32_t sm[7][kThreads];
+  int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {-1, -1, -1}, bad = 0;
   for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < g.vox;
        v += (int64_t)gridDim.x * kThreads) {
     const float2 s = S[v];
     if (!(isfinite(s.x) && isfinite(s.y))) {
-      atomicOr(&bbox[6], 1);
+      bad = 1;
       continue;
     }
     if (s.x == 0.f && s.y == 0.f) continue;
@@ -774,8 +942,33 @@ __global__ __launch_bounds__(kThreads) void k_source_bbox(const float2* __restri
     global_coords(v, g, gc[0], gc[1], gc[2]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      atomicMin(&bbox[d], gc[d]);
-      atomicMax(&bbox[3 + d], gc[d]);
+      lo[d] = min(lo[d], gc[d]);
+      hi[d] = max(hi[d], gc[d]);
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    sm[d][threadIdx.x] = lo[d];
+    sm[3 + d][threadIdx.x] = hi[d];
+  }
+  sm[6][threadIdx.x] = bad;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      for (int d = 0; d < 3; ++d) {
+        sm[d][threadIdx.x] = min(sm[d][threadIdx.x], sm[d][threadIdx.x + off]);
+        sm[3 + d][threadIdx.x] = max(sm[3 + d][threadIdx.x], sm[3 + d][threadIdx.x + off]);
+      }
+      sm[6][threadIdx.x] |= sm[6][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (sm[6][0]) atomicOr(&bbox[6], 1);
+    if (sm[3][0] >= 0) {
+      for (int d = 0; d < 3; ++d) {
+        atomicMin(&bbox[d], sm[d][0]);
+        atomicMax(&bbox[3 + d], sm[3 + d][0]);
+      }
     }
   }
 }
@@ -943,16 +1136,23 @@ hipError_t launch_last_pass(const SlotDesc* tab, int nslots, const Geo& g, const
   return hipGetLastError();
 }
 
+static inline unsigned persistent_grid(int64_t ntiles, const Geo& g, int threads) {
+  // two resident workgroups per compute unit (one for 512-thread tiles limited to 2 waves/SIMD)
+  const int per_cu = (threads == 512 && MBS_COL_WAVES_BIG < 4) ? 1 : 2;
+  const int64_t cap = (int64_t)per_cu * (g.cus > 0 ? g.cus : 256);
+  return (unsigned)(ntiles < cap ? ntiles : cap);
+}
+
 hipError_t launch_mid_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
                            int inverse, hipStream_t s) {
   const int WC = cols_per_tile_c(g.n[1]);
-  const int64_t blocks = (int64_t)g.S * g.n[0] * ((g.n[2] + WC - 1) / WC);
-  dim3 grid((unsigned)blocks, nslots);
+  const int64_t ntiles = (int64_t)g.S * g.n[0] * ((g.n[2] + WC - 1) / WC);
+  dim3 grid(persistent_grid(ntiles, g, col_threads_c(g.n[1])), nslots);
   switch (g.n[1]) {
-#define MBS_CASE(NN)                                                                  \
-  case NN:                                                                            \
-    if (inverse) hipLaunchKernelGGL((k_mid<NN, 1>), grid, dim3(kThreads), 0, s, tab, g, tb); \
-    else hipLaunchKernelGGL((k_mid<NN, -1>), grid, dim3(kThreads), 0, s, tab, g, tb);        \
+#define MBS_CASE(NN)                                                                              \
+  case NN:                                                                                        \
+    if (inverse) hipLaunchKernelGGL((k_col<NN, 1>), grid, dim3(col_threads_c(NN)), 0, s, tab, g, tb, ntiles); \
+    else hipLaunchKernelGGL((k_col<NN, 0>), grid, dim3(col_threads_c(NN)), 0, s, tab, g, tb, ntiles);         \
     break;
     MBS_FOR_EACH_N(MBS_CASE)
 #undef MBS_CASE
@@ -965,11 +1165,11 @@ hipError_t launch_mid_pass(const SlotDesc* tab, int nslots, const Geo& g, const 
 hipError_t launch_green_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
                              hipStream_t s) {
   const int WC = cols_per_tile_c(g.n[0]);
-  const int64_t blocks = (int64_t)g.S * g.n[1] * ((g.n[2] + WC - 1) / WC);
-  dim3 grid((unsigned)blocks, nslots);
+  const int64_t ntiles = (int64_t)g.S * g.n[1] * ((g.n[2] + WC - 1) / WC);
+  dim3 grid(persistent_grid(ntiles, g, col_threads_c(g.n[0])), nslots);
   switch (g.n[0]) {
 #define MBS_CASE(NN) \
-  case NN: hipLaunchKernelGGL(k_green<NN>, grid, dim3(kThreads), 0, s, tab, g, tb); break;
+  case NN: hipLaunchKernelGGL((k_col<NN, 2>), grid, dim3(col_threads_c(NN)), 0, s, tab, g, tb, ntiles); break;
     MBS_FOR_EACH_N(MBS_CASE)
 #undef MBS_CASE
     default:
@@ -1010,7 +1210,8 @@ hipError_t launch_face(const SlotDesc* tab, int nslots, const Geo& g, hipStream_
 hipError_t launch_reduce(const SlotDesc* tab, int nslots, const Geo& g, int64_t n_main,
                          int64_t n_face, hipStream_t s) {
   (void)g;
-  hipLaunchKernelGGL(k_reduce, dim3(nslots), dim3(kThreads), 0, s, tab, n_main, n_face);
+  hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks, nslots), dim3(kThreads), 0, s, tab, n_main, n_face);
+  hipLaunchKernelGGL(k_reduce2, dim3(nslots), dim3(64), 0, s, tab);
   return hipGetLastError();
 }
 
@@ -1043,7 +1244,7 @@ hipError_t launch_medium_B(const float2* n, const Geo& g, double k0sq, const int
 }
 
 hipError_t launch_source_bbox(const float2* S, const Geo& g, int32_t* bbox, hipStream_t s) {
-  hipLaunchKernelGGL(k_source_bbox, dim3(grid_1d(g.vox)), dim3(kThreads), 0, s, S, g, bbox);
+  hipLaunchKernelGGL(k_source_bbox, dim3(grid_1d(g.vox, 8192)), dim3(kThreads), 0, s, S, g, bbox);
   return hipGetLastError();
 }
 

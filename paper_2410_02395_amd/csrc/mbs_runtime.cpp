@@ -86,6 +86,7 @@ struct Slot {
   double* part_main = nullptr;
   double* part_face = nullptr;
   double* hist = nullptr;
+  double* part_red = nullptr;
   bool has_medium = false;
   bool has_source = false;
   bool busy = false;       // a solve was started and has not been collected
@@ -96,6 +97,8 @@ struct Slot {
   double rho_ref = 0;
   int32_t last_status = MBS_OK;
   int64_t start_seq = 0;   // chunks launched before this solve started
+  int64_t launched = 0;    // iterations enqueued since the solve started
+  int32_t max_iter = 0;
   mbs_result res{};
 };
 
@@ -234,7 +237,7 @@ size_t slot_bytes(const Geo& g) {
     if (g.a[d]) b += 4 * (size_t)slab_elems(g, d) * sizeof(float2);
   b += default_ybox(g) * sizeof(float2);
   b += (size_t)(last_pass_blocks(g) + face_blocks(g) + 1) * sizeof(double);
-  b += (size_t)kHistCap * sizeof(double);
+  b += (size_t)(kHistCap + kReduceBlocks) * sizeof(double);
   return b;
 }
 
@@ -272,6 +275,7 @@ void fill_desc(mbs_plan p, int i) {
   d.part_main = s.part_main;
   d.part_face = s.part_face;
   d.hist = s.hist;
+  d.part_red = s.part_red;
   d.active = 1;
 }
 
@@ -359,15 +363,23 @@ mbs_status build_graph(mbs_plan p) {
 
 // enqueue check_every iterations for all slots, then copy the slot states to the host
 mbs_status launch_chunk(mbs_plan p) {
+  int64_t n_it = p->check_every;
   if (p->use_graph) {
     mbs_status st = build_graph(p);
     if (st != MBS_OK) return st;
     HIP_TRY(hipGraphLaunch(p->graph, p->stream));
   } else {
+    // eager launches: no more iterations than the running slots can still use
+    int64_t need = 0;
+    for (auto& s : p->slots)
+      if (s.busy && !s.finishing) need = std::max(need, (int64_t)s.max_iter - s.launched);
+    n_it = std::max<int64_t>(1, std::min<int64_t>(p->check_every, need));
     p->tcount = 0;
-    for (int it = 0; it < p->check_every; ++it)
+    for (int64_t it = 0; it < n_it; ++it)
       HIP_TRY(enqueue_iteration(p, p->d_tab, p->nslots, p->stream));
   }
+  for (auto& s : p->slots)
+    if (s.busy && !s.finishing) s.launched += n_it;
   p->cur_buf ^= 1;
   SlotState* hb = p->h_states + p->cur_buf * (p->nslots + 1);
   HIP_TRY(hipMemcpyAsync(hb, p->d_states, sizeof(SlotState) * p->nslots, hipMemcpyDeviceToHost, p->stream));
@@ -662,6 +674,11 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
     return s;
   };
   if (hipGetDevice(&p->device) != hipSuccess) return fail(MBS_EHIP);
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) return fail(MBS_EHIP);
+    p->geo.cus = cus;
+  }
   if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(MBS_EHIP);
   if (hipEventCreateWithFlags(&p->chunk_ev, hipEventDisableTiming) != hipSuccess) return fail(MBS_EHIP);
   // tables: twiddles, |p|^2 per axis, correction block (FP64 on the host, rounded once)
@@ -714,6 +731,7 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
     if ((st = dalloc(p, &s.part_main, p->n_main)) != MBS_OK) return fail(st);
     if ((st = dalloc(p, &s.part_face, p->n_face)) != MBS_OK) return fail(st);
     if ((st = dalloc(p, &s.hist, kHistCap)) != MBS_OK) return fail(st);
+    if ((st = dalloc(p, &s.part_red, kReduceBlocks)) != MBS_OK) return fail(st);
     if (hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming) != hipSuccess) return fail(MBS_EHIP);
   }
   if ((st = dalloc(p, &p->d_tab, p->nslots)) != MBS_OK) return fail(st);

@@ -15,7 +15,7 @@ from typing import Optional, Sequence
 import torch  # noqa: F401  (loads the HIP runtime torch was built with before libmbs)
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libmbs.so")
+LIB_PATH = os.environ.get("MBS_LIBRARY", os.path.join(PKG, "libmbs.so"))
 
 EXPORTS = (
     "mbs_plan_bytes", "mbs_plan_create", "mbs_plan_destroy", "mbs_set_medium", "mbs_solve",
