@@ -24,6 +24,14 @@
 
 namespace mbs {
 
+// Pointers read from the slot table are generic; casting them to the global address
+// space makes the compiler emit global (not flat) loads and stores, which do not
+// count against the LDS wait counter and so stay in flight across LDS barriers.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // ---------------------------------------------------------------------------
 // complex helpers (float2 = interleaved re, im)
 // ---------------------------------------------------------------------------
@@ -140,6 +148,16 @@ __host__ __device__ constexpr int plan_ns(int n, int s, bool rev) {
   return p;
 }
 
+// keeps registers allocated up to this point (no instruction is emitted); used so that the
+// next tile's loads do not land in registers a pending store still has to read
+template <int PER, int R>
+__device__ __forceinline__ void keep_alive(const float2 (&v)[PER][R]) {
+#pragma unroll
+  for (int q = 0; q < PER; ++q)
+#pragma unroll
+    for (int m = 0; m < R; ++m) asm volatile("" ::"v"(v[q][m].x), "v"(v[q][m].y));
+}
+
 // barrier for LDS traffic only: waits for this wave's LDS operations, not for its
 // outstanding global loads, so prefetches stay in flight across FFT stages
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
@@ -176,9 +194,6 @@ __host__ __device__ constexpr int col_threads_c(int n) { return n >= 384 ? 512 :
 // minimum waves per SIMD requested for the column tiles (register budget per thread)
 #ifndef MBS_COL_WAVES_BIG
 #define MBS_COL_WAVES_BIG 2
-#endif
-#ifndef MBS_COL_PREFETCH
-#define MBS_COL_PREFETCH 1
 #endif
 __host__ __device__ constexpr int col_waves_c(int n) { return col_threads_c(n) == 512 ? MBS_COL_WAVES_BIG : 2; }
 
@@ -275,29 +290,47 @@ __device__ __forceinline__ void lds_stages(float2* lds, const float2* __restrict
   }
 }
 
-// Whole FFT of a tile.  `in` holds the inputs of stage 0 (elements i + m N/R0 of this
-// thread's butterflies), `out` receives the outputs of the last stage (elements
-// i + m N/RL, natural order).  Starts with a barrier, so the caller may have been
-// reading LDS just before.
+// First stage of an FFT: butterflies of `in` (stage-0 inputs, elements i + m N/R0 of this
+// thread's butterflies) in registers, outputs written to LDS.  Starts with a barrier so the
+// caller may have been reading LDS just before.  For a one-stage plan nothing goes to LDS.
+template <class Tile, int N, bool REV, int SIGN, int PER0, int R0>
+__device__ __forceinline__ void fft_head(float2 (&in)[PER0][R0], float2* lds, const float2* __restrict__ tw,
+                                         int tid) {
+  constexpr int P = plan_len(N);
+  static_assert(R0 == plan_radix(N, 0, REV), "plan mismatch");
+  bfly_regs<Tile, N, R0, 1, SIGN, PER0>(in, tw, tid);
+  if constexpr (P > 1) {
+    lds_barrier();
+    put_lds<Tile, N, R0, 1, PER0>(lds, in, tid);
+    lds_barrier();
+  }
+}
+
+// Remaining stages: the middle ones in LDS, the last one read into `out` (outputs at
+// i + m N/RL, natural order).  For a one-stage plan `in` already holds the result.
 template <class Tile, int N, bool REV, int SIGN, int PER0, int R0, int PERL, int RL>
-__device__ __forceinline__ void fft_tile(float2 (&in)[PER0][R0], float2 (&out)[PERL][RL], float2* lds,
+__device__ __forceinline__ void fft_tail(float2 (&in)[PER0][R0], float2 (&out)[PERL][RL], float2* lds,
                                          const float2* __restrict__ tw, int tid) {
   constexpr int P = plan_len(N);
-  static_assert(R0 == plan_radix(N, 0, REV) && RL == plan_radix(N, P - 1, REV), "plan mismatch");
-  bfly_regs<Tile, N, R0, 1, SIGN, PER0>(in, tw, tid);
+  static_assert(RL == plan_radix(N, P - 1, REV), "plan mismatch");
   if constexpr (P == 1) {
 #pragma unroll
     for (int q = 0; q < PER0; ++q)
 #pragma unroll
       for (int m = 0; m < R0; ++m) out[q][m] = in[q][m];
   } else {
-    lds_barrier();
-    put_lds<Tile, N, R0, 1, PER0>(lds, in, tid);
-    lds_barrier();
     lds_stages<Tile, N, REV, SIGN, 1, P - 1>(lds, tw, tid);
     get_lds<Tile, N, RL, PERL>(lds, out, tid);
     bfly_regs<Tile, N, RL, plan_ns(N, P - 1, REV), SIGN, PERL>(out, tw, tid);
   }
+}
+
+// Whole FFT of a tile (head then tail).
+template <class Tile, int N, bool REV, int SIGN, int PER0, int R0, int PERL, int RL>
+__device__ __forceinline__ void fft_tile(float2 (&in)[PER0][R0], float2 (&out)[PERL][RL], float2* lds,
+                                         const float2* __restrict__ tw, int tid) {
+  fft_head<Tile, N, REV, SIGN, PER0, R0>(in, lds, tw, tid);
+  fft_tail<Tile, N, REV, SIGN, PER0, R0, PERL, RL>(in, out, lds, tw, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -402,6 +435,13 @@ __global__ __launch_bounds__(kThreads) void k_first(const SlotDesc* __restrict__
   __syncthreads();
   const int t = g.t;
   const int64_t plane2 = (int64_t)g.n[0] * g.n[1];
+  const auto X = gp(sd.x);
+  const auto Bm = gp(sd.B);
+  const auto E0 = gp(sd.slab[0][2]);
+  const auto E1 = gp(sd.slab[1][2]);
+  const auto E2 = gp(sd.slab[2][2]);
+  const auto Y = gp(sd.ybox);
+  const auto W = gp(sd.W);
   float2 v[PER0][R0];
 #pragma unroll
   for (int q = 0; q < PER0; ++q) {
@@ -415,14 +455,14 @@ __global__ __launch_bounds__(kThreads) void k_first(const SlotDesc* __restrict__
       float2 w = make_float2(0.f, 0.f);
       if (ok && li.valid) {
         const int64_t gi = li.gbase + j;
-        w = cmul(sd.B[gi], sd.x[gi]);
-        if (li.e0 >= 0) w = cadd(w, sd.slab[0][2][li.e0 + j]);
-        if (li.e1 >= 0) w = cadd(w, sd.slab[1][2][li.e1 + j]);
+        w = cmul(Bm[gi], X[gi]);
+        if (li.e0 >= 0) w = cadd(w, E0[li.e0 + j]);
+        if (li.e1 >= 0) w = cadd(w, E1[li.e1 + j]);
         if (li.e2 >= 0) {
-          if (j < t) w = cadd(w, sd.slab[2][2][li.e2 + (int64_t)j * plane2]);
-          else if (j >= N - t) w = cadd(w, sd.slab[2][2][li.e2 + (int64_t)(t + j - (N - t)) * plane2]);
+          if (j < t) w = cadd(w, E2[li.e2 + (int64_t)j * plane2]);
+          else if (j >= N - t) w = cadd(w, E2[li.e2 + (int64_t)(t + j - (N - t)) * plane2]);
         }
-        if (j >= li.jlo && j < li.jhi) w = cadd(w, sd.ybox[li.ybase + j]);
+        if (j >= li.jlo && j < li.jhi) w = cadd(w, Y[li.ybase + j]);
       }
       v[q][m] = w;
     }
@@ -436,7 +476,7 @@ __global__ __launch_bounds__(kThreads) void k_first(const SlotDesc* __restrict__
     Tile::template bf<RL>(tid + q * kThreads, i, l);
     if (!info[l].valid) continue;
 #pragma unroll
-    for (int m = 0; m < RL; ++m) sd.W[info[l].gbase + i + m * (N / RL)] = o[q][m];
+    for (int m = 0; m < RL; ++m) W[info[l].gbase + i + m * (N / RL)] = o[q][m];
   }
 }
 
@@ -461,6 +501,12 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
   const int64_t line0 = (int64_t)blockIdx.x * L;
   for (int l = tid; l < L; l += kThreads) line_info(line0 + l, g, sd, info[l]);
   __syncthreads();
+  const auto X = gp(sd.x);
+  const auto Bm = gp(sd.B);
+  const auto W = gp(sd.W);
+  const auto U0 = gp(sd.slab[0][1]);
+  const auto U1 = gp(sd.slab[1][1]);
+  const auto U2 = gp(sd.slab[2][1]);
   float2 v[PER0][R0];
 #pragma unroll
   for (int q = 0; q < PER0; ++q) {
@@ -470,7 +516,7 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
     const LineInfo& li = info[ok ? l : 0];
 #pragma unroll
     for (int m = 0; m < R0; ++m)
-      v[q][m] = (ok && li.valid) ? sd.W[li.gbase + i + m * (N / R0)] : make_float2(0.f, 0.f);
+      v[q][m] = (ok && li.valid) ? W[li.gbase + i + m * (N / R0)] : make_float2(0.f, 0.f);
   }
   float2 o[PERL][RL];
   fft_tile<Tile, N, false, +1>(v, o, lds, tb.tw[2], tid);
@@ -489,22 +535,22 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
     for (int m = 0; m < RL; ++m) {
       const int j = i + m * (N / RL);
       const int64_t gi = li.gbase + j;
-      const float2 xv = sd.x[gi];
+      const float2 xv = X[gi];
       const float2 u = csub(xv, o[q][m]);
-      const float2 bu = cmul(sd.B[gi], u);
-      sd.x[gi] = make_float2(xv.x - alpha * bu.x, xv.y - alpha * bu.y);
+      const float2 bu = cmul(Bm[gi], u);
+      X[gi] = make_float2(xv.x - alpha * bu.x, xv.y - alpha * bu.y);
       bool edge = false;
-      if (li.e0 >= 0) { sd.slab[0][1][li.e0 + j] = u; edge = true; }
-      if (li.e1 >= 0) { sd.slab[1][1][li.e1 + j] = u; edge = true; }
+      if (li.e0 >= 0) { U0[li.e0 + j] = u; edge = true; }
+      if (li.e1 >= 0) { U1[li.e1 + j] = u; edge = true; }
       if (li.e2 >= 0) {
-        if (j < t) { sd.slab[2][1][li.e2 + (int64_t)j * plane2] = u; edge = true; }
-        else if (j >= N - t) { sd.slab[2][1][li.e2 + (int64_t)(t + j - (N - t)) * plane2] = u; edge = true; }
+        if (j < t) { U2[li.e2 + (int64_t)j * plane2] = u; edge = true; }
+        else if (j >= N - t) { U2[li.e2 + (int64_t)(t + j - (N - t)) * plane2] = u; edge = true; }
       }
       if (!edge) acc += (double)bu.x * bu.x + (double)bu.y * bu.y;
     }
   }
   const double s = block_sum(acc, red);
-  if (tid == 0) sd.part_main[blockIdx.x] = s;
+  if (tid == 0) gp(sd.part_main)[blockIdx.x] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -513,18 +559,117 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
 // Persistent workgroups walk the tiles; the loads of the next tile are issued
 // before the LDS stages of the current one so that HBM traffic and LDS work overlap.
 // ---------------------------------------------------------------------------
-template <int N, int WC, int R, int PER>
-__device__ __forceinline__ void load_cols(float2 (&v)[PER][R], const float2* __restrict__ W, int64_t base,
-                                          int64_t stride, int ncols, int tid) {
+template <int N, int WC, int R, int PER, bool FULL, class Ptr>
+__device__ __forceinline__ void load_cols(float2 (&v)[PER][R], Ptr W, int64_t base, int64_t stride, int ncols,
+                                          int tid) {
   using Tile = ColTile<N, WC>;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const bool ok = bvalid<Tile, R>(q, tid);
     int i = 0, c = 0;
     if (ok) Tile::template bf<R>(tid + q * Tile::NT, i, c);
+    const bool in = ok && (FULL || c < ncols);
 #pragma unroll
-    for (int m = 0; m < R; ++m)
-      v[q][m] = (ok && c < ncols) ? W[base + (int64_t)(i + m * (N / R)) * stride + c] : make_float2(0.f, 0.f);
+    for (int m = 0; m < R; ++m) {
+      if (FULL) v[q][m] = W[base + (int64_t)(i + m * (N / R)) * stride + c];
+      else v[q][m] = in ? W[base + (int64_t)(i + m * (N / R)) * stride + c] : make_float2(0.f, 0.f);
+    }
+  }
+}
+
+// The persistent loop over this workgroup's tiles.  FULL: every tile has WC valid columns,
+// so loads and stores need no per-lane masks (no divergent branches inside the loop).
+template <int N, int KIND, bool FULL, class Ptr>
+__device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, int64_t tile, int64_t ntiles,
+                                         float2* lds, const float2* s_tw, const float* s_p2x, const float* s_p2y,
+                                         const float* s_p2z, float kb2, float cim, float inv) {
+  constexpr int WC = cols_per_tile_c(N);
+  using Tile = ColTile<N, WC>;
+  constexpr int P = plan_len(N);
+  constexpr int R0 = plan_radix(N, 0, false), RL = plan_radix(N, P - 1, false);
+  constexpr int PER0 = per_thread<Tile, R0>(), PERL = per_thread<Tile, RL>();
+  const int tid = threadIdx.x;
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+  const int CB = (n2 + WC - 1) / WC;
+  const int nfix = KIND == 2 ? n1 : n0;
+  const int64_t stride = KIND == 2 ? (int64_t)n1 * n2 : (int64_t)n2;
+  // tile t = (s * nfix + fix) * CB + cb, walked with a stride of gridDim.x without divisions
+  int cb = (int)(tile % CB), fix = (int)((tile / CB) % nfix), sub = (int)(tile / ((int64_t)CB * nfix));
+  const int gcb = (int)(gridDim.x % CB), grest = (int)(gridDim.x / CB);
+  const int gfix = grest % nfix, gsub = grest / nfix;
+  auto tile_base = [&](int s_, int fix_, int cb_) -> int64_t {
+    return KIND == 2 ? ((int64_t)s_ * N * n1 + fix_) * n2 + cb_ * WC
+                     : (((int64_t)s_ * n0 + fix_) * N) * n2 + cb_ * WC;
+  };
+  int c0 = cb * WC, ncols = min(WC, n2 - c0);
+  int64_t base = tile_base(sub, fix, cb);
+  float2 cur[PER0][R0];
+  load_cols<N, WC, R0, PER0, FULL>(cur, W, base, stride, ncols, tid);
+  fft_head<Tile, N, false, KIND == 1 ? +1 : -1, PER0, R0>(cur, lds, s_tw, tid);
+  // output registers of the previous tile (the FFT result that is stored)
+  constexpr int PERO = KIND == 2 ? PER0 : PERL;
+  constexpr int RO = KIND == 2 ? R0 : RL;
+  float2 o[PERO][RO];
+#pragma unroll
+  for (int q = 0; q < PERO; ++q)
+#pragma unroll
+    for (int m = 0; m < RO; ++m) o[q][m] = make_float2(0.f, 0.f);
+  for (;;) {
+    const int64_t next = tile + gridDim.x;
+    const bool more = next < ntiles;
+    int ncb = cb + gcb, nfx = fix + gfix, nsub = sub + gsub;
+    if (ncb >= CB) { ncb -= CB; ++nfx; }
+    if (nfx >= nfix) { nfx -= nfix; ++nsub; }
+    const int nc0 = ncb * WC, nncols = min(WC, n2 - nc0);
+    const int64_t nbase = tile_base(nsub, nfx, ncb);
+    float2 nxt[PER0][R0];
+    if (more) load_cols<N, WC, R0, PER0, FULL>(nxt, W, nbase, stride, nncols, tid);
+    keep_alive(o);
+    if constexpr (KIND == 2) {
+      float2 f[PERL][RL];
+      fft_tail<Tile, N, false, -1, PER0, R0, PERL, RL>(cur, f, lds, s_tw, tid);
+      // (L + I)^-1 = 1 / (1 + c (k_b^2 - |p|^2)), c = i c_im, with the 1/(n0 n1 n2) of the inverse
+      const float p21 = s_p2y[fix];
+#pragma unroll
+      for (int q = 0; q < PERL; ++q) {
+        if (!bvalid<Tile, RL>(q, tid)) continue;
+        int i, c;
+        Tile::template bf<RL>(tid + q * Tile::NT, i, c);
+        const float p2z = s_p2z[c < ncols ? c0 + c : 0];
+#pragma unroll
+        for (int m = 0; m < RL; ++m) {
+          const float Pp = s_p2x[i + m * (N / RL)] + p21 + p2z;
+          const float E = cim * (kb2 - Pp);
+          const float den = inv / (1.f + E * E);
+          f[q][m] = cmul(f[q][m], make_float2(den, -E * den));
+        }
+      }
+      fft_tile<Tile, N, true, +1>(f, o, lds, s_tw, tid);
+    } else {
+      fft_tail<Tile, N, false, KIND == 1 ? +1 : -1, PER0, R0, PERL, RL>(cur, o, lds, s_tw, tid);
+    }
+#pragma unroll
+    for (int q = 0; q < PERO; ++q) {
+      if (!bvalid<Tile, RO>(q, tid)) continue;
+      int i, c;
+      Tile::template bf<RO>(tid + q * Tile::NT, i, c);
+      if (!FULL && c >= ncols) continue;
+#pragma unroll
+      for (int m = 0; m < RO; ++m) W[base + (int64_t)(i + m * (N / RO)) * stride + c] = o[q][m];
+    }
+    if (!more) break;
+    fft_head<Tile, N, false, KIND == 1 ? +1 : -1, PER0, R0>(nxt, lds, s_tw, tid);
+#pragma unroll
+    for (int q = 0; q < PER0; ++q)
+#pragma unroll
+      for (int m = 0; m < R0; ++m) cur[q][m] = nxt[q][m];
+    tile = next;
+    base = nbase;
+    cb = ncb;
+    fix = nfx;
+    sub = nsub;
+    c0 = nc0;
+    ncols = nncols;
   }
 }
 
@@ -541,94 +686,30 @@ __global__ __launch_bounds__(col_threads_c(N), col_waves_c(N)) void k_col(const 
   constexpr int R0 = plan_radix(N, 0, false), RL = plan_radix(N, P - 1, false);
   constexpr int PER0 = per_thread<Tile, R0>(), PERL = per_thread<Tile, RL>();
   __shared__ float2 lds[Tile::LDS];
+  // twiddles and |p|^2 tables live in LDS for the whole persistent loop: the only global
+  // loads in flight are then the next tile's data, so waits on them stay precise
+  __shared__ float2 s_tw[N];
+  __shared__ float s_p2x[KIND == 2 ? N : 1];
+  __shared__ float s_p2z[KIND == 2 ? 1024 : 1];
+  __shared__ float s_p2y[KIND == 2 ? 1024 : 1];
   const int tid = threadIdx.x;
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
-  const int CB = (n2 + WC - 1) / WC;
-  const int nfix = KIND == 2 ? n1 : n0;   // the tile's fixed coordinate runs over y (x pass) or x (y pass)
-  const int64_t stride = KIND == 2 ? (int64_t)n1 * n2 : (int64_t)n2;
-  float2* __restrict__ W = sd.W;
-  const float kb2 = sd.kb2, cim = sd.c_im, inv = sd.inv_vox;
-  auto locate = [&](int64_t tl, int& c0, int& ncols, int& fix) -> int64_t {
-    const int cb = (int)(tl % CB);
-    const int64_t rest = tl / CB;
-    fix = (int)(rest % nfix);
-    const int s = (int)(rest / nfix);
-    c0 = cb * WC;
-    ncols = min(WC, n2 - c0);
-    return KIND == 2 ? ((int64_t)s * N * n1 + fix) * n2 + c0 : (((int64_t)s * n0 + fix) * N) * n2 + c0;
-  };
-  int c0, ncols, fix;
-  int64_t base = locate(tile, c0, ncols, fix);
-  float2 cur[PER0][R0];
-  load_cols<N, WC, R0, PER0>(cur, W, base, stride, ncols, tid);
-  for (;;) {
-    const int64_t next = tile + gridDim.x;
-    const bool more = next < ntiles;
-    int nc0 = 0, nncols = 0, nfx = 0;
-    int64_t nbase = 0;
-    float2 nxt[PER0][R0];
-    if (MBS_COL_PREFETCH && more) {
-      nbase = locate(next, nc0, nncols, nfx);
-      load_cols<N, WC, R0, PER0>(nxt, W, nbase, stride, nncols, tid);
-    }
+  {
+    const float2* twg = KIND == 2 ? tb.tw[0] : tb.tw[1];
+    for (int i = tid; i < N; i += Tile::NT) s_tw[i] = twg[i];
     if constexpr (KIND == 2) {
-      float2 f[PERL][RL];
-      fft_tile<Tile, N, false, -1>(cur, f, lds, tb.tw[0], tid);
-      // (L + I)^-1 = 1 / (1 + c (k_b^2 - |p|^2)), c = i c_im, with the 1/(n0 n1 n2) of the inverse
-      const float p21 = tb.p2[1][fix];
-#pragma unroll
-      for (int q = 0; q < PERL; ++q) {
-        if (!bvalid<Tile, RL>(q, tid)) continue;
-        int i, c;
-        Tile::template bf<RL>(tid + q * Tile::NT, i, c);
-        const float p2z = tb.p2[2][c < ncols ? c0 + c : 0];
-#pragma unroll
-        for (int m = 0; m < RL; ++m) {
-          const float Pp = tb.p2[0][i + m * (N / RL)] + p21 + p2z;
-          const float E = cim * (kb2 - Pp);
-          const float den = inv / (1.f + E * E);
-          f[q][m] = cmul(f[q][m], make_float2(den, -E * den));
-        }
-      }
-      float2 o[PER0][R0];
-      fft_tile<Tile, N, true, +1>(f, o, lds, tb.tw[0], tid);
-#pragma unroll
-      for (int q = 0; q < PER0; ++q) {
-        if (!bvalid<Tile, R0>(q, tid)) continue;
-        int i, c;
-        Tile::template bf<R0>(tid + q * Tile::NT, i, c);
-        if (c >= ncols) continue;
-#pragma unroll
-        for (int m = 0; m < R0; ++m) W[base + (int64_t)(i + m * (N / R0)) * stride + c] = o[q][m];
-      }
-    } else {
-      float2 o[PERL][RL];
-      fft_tile<Tile, N, false, KIND == 1 ? +1 : -1>(cur, o, lds, tb.tw[1], tid);
-#pragma unroll
-      for (int q = 0; q < PERL; ++q) {
-        if (!bvalid<Tile, RL>(q, tid)) continue;
-        int i, c;
-        Tile::template bf<RL>(tid + q * Tile::NT, i, c);
-        if (c >= ncols) continue;
-#pragma unroll
-        for (int m = 0; m < RL; ++m) W[base + (int64_t)(i + m * (N / RL)) * stride + c] = o[q][m];
-      }
+      for (int i = tid; i < N; i += Tile::NT) s_p2x[i] = tb.p2[0][i];
+      for (int i = tid; i < n2; i += Tile::NT) s_p2z[i] = tb.p2[2][i];
+      for (int i = tid; i < n1; i += Tile::NT) s_p2y[i] = tb.p2[1][i];
     }
-    if (!more) break;
-    if (!MBS_COL_PREFETCH) {
-      nbase = locate(next, nc0, nncols, nfx);
-      load_cols<N, WC, R0, PER0>(nxt, W, nbase, stride, nncols, tid);
-    }
-#pragma unroll
-    for (int q = 0; q < PER0; ++q)
-#pragma unroll
-      for (int m = 0; m < R0; ++m) cur[q][m] = nxt[q][m];
-    tile = next;
-    base = nbase;
-    c0 = nc0;
-    ncols = nncols;
-    fix = nfx;
   }
+  __syncthreads();
+  const auto W = gp(sd.W);
+  const float kb2 = sd.kb2, cim = sd.c_im, inv = sd.inv_vox;
+  if (n2 % WC == 0)
+    col_loop<N, KIND, true>(W, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv);
+  else
+    col_loop<N, KIND, false>(W, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv);
 }
 
 // ---------------------------------------------------------------------------
@@ -660,8 +741,8 @@ __global__ __launch_bounds__(kThreads) void k_corr(const SlotDesc* __restrict__ 
   const int mul = d == 0 ? g.P[1] * g.P[2] : (d == 1 ? g.P[2] : 1);
   const int s_lo = s + (((sc[d] - 1 + Pd) % Pd) - sc[d]) * mul;
   const int s_hi = s + (((sc[d] + 1) % Pd) - sc[d]) * mul;
-  const float2* __restrict__ src = sd.slab[d][which == 0 ? 0 : 1];
-  float2* __restrict__ dst = sd.slab[d][which == 0 ? 2 : 3];
+  const auto src = gp(sd.slab[d][which == 0 ? 0 : 1]);
+  const auto dst = gp(sd.slab[d][which == 0 ? 2 : 3]);
   float2 dh[T], dl[T];
 #pragma unroll
   for (int b = 0; b < T; ++b) {
@@ -736,22 +817,22 @@ __global__ __launch_bounds__(kThreads) void k_face(const SlotDesc* __restrict__ 
                                    : (k == 1 ? (int64_t)g.n[0] * g.n[2] : (int64_t)g.n[0] * g.n[1]);
       const int64_t ad = (((int64_t)s * 2 + side) * t + aa) * plane + (int64_t)p * dq + q;
       addr[k] = ad;
-      esum = cadd(esum, sd.slab[k][3][ad]);
-      u = sd.slab[k][1][ad];
+      esum = cadd(esum, gp(sd.slab[k][3])[ad]);
+      u = gp(sd.slab[k][1])[ad];
     }
     const int64_t gi = (((int64_t)s * g.n[0] + i[0]) * g.n[1] + i[1]) * g.n[2] + i[2];
-    const float2 bu = cmul(sd.B[gi], u);
+    const float2 bu = cmul(gp(sd.B)[gi], u);
     const float2 dd = cadd(bu, esum);
-    const float2 xv = sd.x[gi];
+    const float2 xv = gp(sd.x)[gi];
     const float2 xn = make_float2(xv.x - sd.alpha * esum.x, xv.y - sd.alpha * esum.y);
-    sd.x[gi] = xn;
+    gp(sd.x)[gi] = xn;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      if (addr[k] >= 0) sd.slab[k][0][addr[k]] = xn;
+      if (addr[k] >= 0) gp(sd.slab[k][0])[addr[k]] = xn;
     acc = (double)dd.x * dd.x + (double)dd.y * dd.y;
   }
   const double ssum = block_sum(acc, red);
-  if (threadIdx.x == 0) sd.part_face[blockIdx.x] = ssum;
+  if (threadIdx.x == 0) gp(sd.part_face)[blockIdx.x] = ssum;
 }
 
 // ---------------------------------------------------------------------------
@@ -770,9 +851,9 @@ __global__ __launch_bounds__(kThreads) void k_reduce1(const SlotDesc* __restrict
   const int64_t hi = lo + chunk < total ? lo + chunk : total;
   double acc = 0.0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads)
-    acc += i < n_main ? sd.part_main[i] : sd.part_face[i - n_main];
+    acc += i < n_main ? gp(sd.part_main)[i] : gp(sd.part_face)[i - n_main];
   const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) sd.part_red[blockIdx.x] = s;
+  if (threadIdx.x == 0) gp(sd.part_red)[blockIdx.x] = s;
 }
 
 __global__ __launch_bounds__(64) void k_reduce2(const SlotDesc* __restrict__ tab) {
