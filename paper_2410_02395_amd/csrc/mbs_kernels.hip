@@ -27,10 +27,17 @@ namespace mbs {
 // Pointers read from the slot table are generic; casting them to the global address
 // space makes the compiler emit global (not flat) loads and stores, which do not
 // count against the LDS wait counter and so stay in flight across LDS barriers.
+#if defined(__HIP_DEVICE_COMPILE__)
 template <class T>
 __device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
   return (__attribute__((address_space(1))) T*)p;
 }
+#else
+template <class T>
+__device__ __forceinline__ T* gp(T* p) {  // host pass: parsed only, never executed
+  return p;
+}
+#endif
 
 // ---------------------------------------------------------------------------
 // complex helpers (float2 = interleaved re, im)
@@ -560,8 +567,8 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
 // before the LDS stages of the current one so that HBM traffic and LDS work overlap.
 // ---------------------------------------------------------------------------
 template <int N, int WC, int R, int PER, bool FULL, class Ptr>
-__device__ __forceinline__ void load_cols(float2 (&v)[PER][R], Ptr W, int64_t base, int64_t stride, int ncols,
-                                          int tid) {
+__device__ __forceinline__ void load_cols(float2 (&v)[PER][R], Ptr tp, int stride, int ncols, int tid) {
+  // tp: first element of the tile (uniform); per-lane offsets are 32-bit
   using Tile = ColTile<N, WC>;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -569,10 +576,12 @@ __device__ __forceinline__ void load_cols(float2 (&v)[PER][R], Ptr W, int64_t ba
     int i = 0, c = 0;
     if (ok) Tile::template bf<R>(tid + q * Tile::NT, i, c);
     const bool in = ok && (FULL || c < ncols);
+    const int o0 = i * stride + c;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      if (FULL) v[q][m] = W[base + (int64_t)(i + m * (N / R)) * stride + c];
-      else v[q][m] = in ? W[base + (int64_t)(i + m * (N / R)) * stride + c] : make_float2(0.f, 0.f);
+      const int o = o0 + m * (N / R) * stride;
+      if (FULL) v[q][m] = tp[o];
+      else v[q][m] = in ? tp[o] : make_float2(0.f, 0.f);
     }
   }
 }
@@ -592,7 +601,7 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
   const int CB = (n2 + WC - 1) / WC;
   const int nfix = KIND == 2 ? n1 : n0;
-  const int64_t stride = KIND == 2 ? (int64_t)n1 * n2 : (int64_t)n2;
+  const int stride = KIND == 2 ? n1 * n2 : n2;
   // tile t = (s * nfix + fix) * CB + cb, walked with a stride of gridDim.x without divisions
   int cb = (int)(tile % CB), fix = (int)((tile / CB) % nfix), sub = (int)(tile / ((int64_t)CB * nfix));
   const int gcb = (int)(gridDim.x % CB), grest = (int)(gridDim.x / CB);
@@ -604,7 +613,7 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
   int c0 = cb * WC, ncols = min(WC, n2 - c0);
   int64_t base = tile_base(sub, fix, cb);
   float2 cur[PER0][R0];
-  load_cols<N, WC, R0, PER0, FULL>(cur, W, base, stride, ncols, tid);
+  load_cols<N, WC, R0, PER0, FULL>(cur, W + base, stride, ncols, tid);
   fft_head<Tile, N, false, KIND == 1 ? +1 : -1, PER0, R0>(cur, lds, s_tw, tid);
   // output registers of the previous tile (the FFT result that is stored)
   constexpr int PERO = KIND == 2 ? PER0 : PERL;
@@ -623,7 +632,7 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
     const int nc0 = ncb * WC, nncols = min(WC, n2 - nc0);
     const int64_t nbase = tile_base(nsub, nfx, ncb);
     float2 nxt[PER0][R0];
-    if (more) load_cols<N, WC, R0, PER0, FULL>(nxt, W, nbase, stride, nncols, tid);
+    if (more) load_cols<N, WC, R0, PER0, FULL>(nxt, W + nbase, stride, nncols, tid);
     keep_alive(o);
     if constexpr (KIND == 2) {
       float2 f[PERL][RL];
@@ -640,7 +649,7 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
         for (int m = 0; m < RL; ++m) {
           const float Pp = s_p2x[i + m * (N / RL)] + p21 + p2z;
           const float E = cim * (kb2 - Pp);
-          const float den = inv / (1.f + E * E);
+          const float den = inv * __builtin_amdgcn_rcpf(1.f + E * E);  // 1 ulp reciprocal
           f[q][m] = cmul(f[q][m], make_float2(den, -E * den));
         }
       }
@@ -654,8 +663,10 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
       int i, c;
       Tile::template bf<RO>(tid + q * Tile::NT, i, c);
       if (!FULL && c >= ncols) continue;
+      const auto tp = W + base;
+      const int o0 = i * stride + c;
 #pragma unroll
-      for (int m = 0; m < RO; ++m) W[base + (int64_t)(i + m * (N / RO)) * stride + c] = o[q][m];
+      for (int m = 0; m < RO; ++m) tp[o0 + m * (N / RO) * stride] = o[q][m];
     }
     if (!more) break;
     fft_head<Tile, N, false, KIND == 1 ? +1 : -1, PER0, R0>(nxt, lds, s_tw, tid);
