@@ -50,7 +50,7 @@ def face_voxels(n, t, a):
     return n[0] * n[1] * n[2] - inner
 
 
-def algorithmic_bytes(shape, split, periodic, t, src_box):
+def algorithmic_bytes(shape, split, periodic, t, src_box, fused=True):
     """Compulsory HBM bytes per launch of each kernel kind for one slot."""
     n = [shape[d] // split[d] for d in range(3)]
     S = split[0] * split[1] * split[2]
@@ -61,6 +61,25 @@ def algorithmic_bytes(shape, split, periodic, t, src_box):
     L = 2048 // n[2] if n[2] < 2048 else 1
     n_main = (S * n[0] * n[1] + L - 1) // L
     n_face = (fv + 255) // 256
+    if fused:
+        # x/y edge-slab lines (whole lines), per subdomain column
+        in0 = n[0] - 2 * t if a[0] else n[0]
+        in1 = n[1] - 2 * t if a[1] else n[1]
+        SLV = S * (n[0] * n[1] - in0 * in1) * n[2]
+        slabs01 = sum(slab_elems(n, S, t, a, d) for d in range(2))
+        return {
+            # w-pass on the x/y edge-slab lines: read x, B, Ex_0/Ex_1; write W
+            "first_z": 24 * SLV + 8 * slabs01 + 8 * src_box,
+            "mid_y_fwd": 16 * V,
+            "green_x": 16 * V,
+            "mid_y_inv": 16 * V,
+            # fused z pass: read W, x, B; write x, W (d on edge lines), U slabs
+            "last_z": 40 * V + 8 * slabs01 + 8 * n_main,
+            "edge_corr": 16 * slabs01 // 2 if slabs01 else 0,
+            # read d, x, Eu; write x, X slabs
+            "face": 8 * (3 * SLV + slabs01) + 8 * ((SLV + 255) // 256),
+            "reduce": 8 * (n_main + (SLV + 255) // 256),
+        }
     return {
         # read x, B (+ edge corrections, source box), write W
         "first_z": 24 * V + 8 * slabs + 8 * src_box,
@@ -184,6 +203,8 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="run the mixed-size request-stream benchmark instead of the 1024^3 iteration")
     ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--no-fusion", action="store_true",
+                    help="separate last inverse and next forward z passes (for comparison)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: every subdomain of the workload is resident on a single "
@@ -215,7 +236,8 @@ def main():
     for d in range(3):
         box *= int(nz[:, d].max() - nz[:, d].min() + 1)
     torch.cuda.synchronize()
-    plan = mbs.Plan(w.shape, w.split, w.periodic, w.t, 1, w.alpha, flags=mbs.MBS_TIMING,
+    flags = mbs.MBS_TIMING | (mbs.MBS_NO_FUSION if args.no_fusion else 0)
+    plan = mbs.Plan(w.shape, w.split, w.periodic, w.t, 1, w.alpha, flags=flags,
                     check_every=min(50, max(1, args.steps)))
     plan.set_medium(0, n, w.k_vac, w.ramp_width, w.ramp_max)
     out = torch.empty(w.shape, dtype=torch.complex64, device=dev)
@@ -234,7 +256,7 @@ def main():
 
     vox = w.voxels
     value = vox * args.steps / dt
-    ab = algorithmic_bytes(w.shape, w.split, w.periodic, w.t, box)
+    ab = algorithmic_bytes(w.shape, w.split, w.periodic, w.t, box, fused=not args.no_fusion)
     kernels = {}
     total_bytes_iter = 0
     for k, (ms, cnt) in tim.items():

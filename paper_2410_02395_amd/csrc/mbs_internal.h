@@ -98,7 +98,15 @@ hipError_t launch_green_pass(const SlotDesc* tab, int nslots, const Geo& g, cons
 hipError_t launch_last_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
                             hipStream_t s);
 hipError_t launch_corr(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, int which,
-                       hipStream_t s);
+                       hipStream_t s, int axis_mask = 7);
+// fused z passes (see mbs_kernels.hip)
+bool fusion_supported(const Geo& g);
+int host_slab_line_count(const Geo& g);
+int64_t slabA_blocks(const Geo& g);
+hipError_t launch_fused(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, hipStream_t s);
+hipError_t launch_wpass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, int slab_only,
+                        hipStream_t s);
+hipError_t launch_slabA(const SlotDesc* tab, int nslots, const Geo& g, hipStream_t s);
 hipError_t launch_face(const SlotDesc* tab, int nslots, const Geo& g, hipStream_t s);
 hipError_t launch_reduce(const SlotDesc* tab, int nslots, const Geo& g, int64_t n_main,
                          int64_t n_face, hipStream_t s);

@@ -45,7 +45,8 @@ __device__ __forceinline__ T* gp(T* p) {  // host pass: parsed only, never execu
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  // explicit fma order: the same product rounds the same way in every kernel
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 // multiply by i*SIGN  (SIGN = -1: -i, SIGN = +1: +i)
@@ -723,6 +724,417 @@ __global__ __launch_bounds__(col_threads_c(N), col_waves_c(N)) void k_col(const 
     col_loop<N, KIND, false>(W, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv);
 }
 
+
+// ---------------------------------------------------------------------------
+// Fused z passes over GLOBAL z-lines: one workgroup holds all P2 subdomain segments
+// of a line of the global grid along z, so the z-axis edge corrections (own
+// wrap-around and the neighbouring segments, Sec. 3.1) come from LDS.
+//   k_fused:  inverse z FFT of iteration n, update x, residual, then w of
+//             iteration n+1 and its forward z FFT (lines outside the x/y edge slabs)
+//   k_wpass:  w = y + B x + edge terms and its forward z FFT (all lines at the start
+//             of a solve, or only the x/y edge-slab lines after they are finished)
+//   k_slabA:  finish x and d on the x/y edge-slab lines
+// ---------------------------------------------------------------------------
+
+// w = y + B x + E with a fixed operation order (E = y + corrections, summed in axis order)
+__device__ __forceinline__ float2 form_w(float2 b, float2 x, float2 e) {
+  return make_float2(fmaf(b.x, x.x, fmaf(-b.y, x.y, e.x)), fmaf(b.x, x.y, fmaf(b.y, x.x, e.y)));
+}
+
+// -c (C (hn - h))[a]  (low edge)  /  -c (C^T (ln - l))[a]  (high edge), with absent
+// neighbours contributing zero; the same arithmetic as k_corr
+__device__ __forceinline__ float2 edge_term(const float2* own, const float2* nb, bool has_nb,
+                                            const float* __restrict__ C, int t, int a, bool high, float cim) {
+  float2 e = make_float2(0.f, 0.f);
+  for (int b = 0; b < t; ++b) {
+    const float2 v = has_nb ? nb[b] : make_float2(0.f, 0.f);
+    const float2 dv = csub(v, own[b]);
+    const float cab = high ? C[b * t + a] : C[a * t + b];
+    e.x = fmaf(cab, dv.x, e.x);
+    e.y = fmaf(cab, dv.y, e.y);
+  }
+  return mul_negc(e, cim);
+}
+
+// x/y edge-slab lines of one column of subdomains (fixed s0, s1): region 0 = i0 in an x slab,
+// region 1 = i0 outside the x slabs and i1 in a y slab
+__device__ __forceinline__ int slab_line_count(const Geo& g) {
+  const int in0 = g.a[0] ? g.n[0] - 2 * g.t : g.n[0];
+  const int in1 = g.a[1] ? g.n[1] - 2 * g.t : g.n[1];
+  return g.n[0] * g.n[1] - in0 * in1;
+}
+__device__ __forceinline__ void slab_line_coords(int k, const Geo& g, int& i0, int& i1) {
+  const int n0 = g.n[0], n1 = g.n[1], t = g.t;
+  if (g.a[0]) {
+    const int r0 = 2 * t * n1;
+    if (k < r0) {
+      const int e = k / n1;
+      i1 = k - e * n1;
+      i0 = e < t ? e : n0 - 2 * t + e;
+      return;
+    }
+    k -= r0;
+    const int e = k / (2 * t), f = k - e * 2 * t;
+    i0 = t + e;
+    i1 = f < t ? f : n1 - 2 * t + f;
+  } else {
+    const int e = k / (2 * t), f = k - e * 2 * t;
+    i0 = e;
+    i1 = f < t ? f : n1 - 2 * t + f;
+  }
+}
+
+// per-workgroup setup of segment-lines: slot l = gl * P2 + s2 holds segment s2 of global line gl
+template <int L, bool SLAB_ONLY>
+__device__ __forceinline__ void global_lines(const Geo& g, const SlotDesc& sd, LineInfo* info, int tid) {
+  const int P2 = g.P[2];
+  const int GL = L / P2;
+  const int per_col = SLAB_ONLY ? slab_line_count(g) : g.n[0] * g.n[1];
+  const int64_t nG = (int64_t)g.P[0] * g.P[1] * per_col;
+  for (int l = tid; l < L; l += kThreads) {
+    const int gl = l / P2, s2 = l - gl * P2;
+    const int64_t G = (int64_t)blockIdx.x * GL + gl;
+    if (G >= nG) {
+      info[l].valid = 0;
+      continue;
+    }
+    const int col = (int)(G / per_col);
+    const int k = (int)(G - (int64_t)col * per_col);
+    int i0, i1;
+    if (SLAB_ONLY) slab_line_coords(k, g, i0, i1);
+    else { i0 = k / g.n[1]; i1 = k - i0 * g.n[1]; }
+    const int s = col * P2 + s2;  // col = s0 * P1 + s1
+    line_info(((int64_t)s * g.n[0] + i0) * g.n[1] + i1, g, sd, info[l]);
+  }
+}
+
+// z-axis neighbour slot of segment slot l (dir = -1 low, +1 high); -1 if absent
+__device__ __forceinline__ int z_neighbour(int l, int dir, const Geo& g) {
+  const int P2 = g.P[2];
+  if (P2 < 2) return -1;
+  const int gl = l / P2, s2 = l - gl * P2;
+  int sn = s2 + dir;
+  if (sn < 0 || sn >= P2) {
+    if (!g.periodic[2]) return -1;
+    sn = (sn + P2) % P2;
+  }
+  return gl * P2 + sn;
+}
+
+// z edge terms of every segment-line from the edge values in zlo / zhi: ez[l][a] is the low
+// edge term of element a, ez[l][t + a] the high edge term of element N - t + a
+template <int L, int TM>
+__device__ __forceinline__ void z_edge_terms(const float2 (*zlo)[TM], const float2 (*zhi)[TM],
+                                             float2 (*ez)[2 * TM], const LineInfo* info, const Geo& g,
+                                             const float* __restrict__ C, float cim, int tid) {
+  const int t = g.t, tt = 2 * t;
+  for (int e = tid; e < L * tt; e += kThreads) {
+    const int l = e / tt, r = e - l * tt;
+    if (!info[l].valid) continue;
+    if (r < t) {
+      const int nb = z_neighbour(l, -1, g);
+      ez[l][r] = edge_term(zhi[l], nb >= 0 ? zhi[nb] : zhi[l], nb >= 0, C, t, r, false, cim);
+    } else {
+      const int nb = z_neighbour(l, +1, g);
+      ez[l][r] = edge_term(zlo[l], nb >= 0 ? zlo[nb] : zlo[l], nb >= 0, C, t, r - t, true, cim);
+    }
+  }
+}
+
+// twiddles of the z FFT and the correction block C into LDS, so the FFT stages and the
+// edge terms wait only on LDS
+template <int N>
+__device__ __forceinline__ void load_line_tables(float2* s_tw, float* s_C, const Tables& tb, const Geo& g,
+                                                 int tid) {
+  for (int e = tid; e < N; e += kThreads) s_tw[e] = tb.tw[2][e];
+  if (g.a[2] > 0)
+    for (int e = tid; e < g.t * g.t; e += kThreads) s_C[e] = tb.C[e];
+}
+
+// this thread's elements i + m N/R (butterfly q, line l) of a subdomain-major array, all loads
+// issued before any is used; lanes of an absent line read line 0 (in bounds, never used)
+template <class Tile, int N, int R, int PER, class Ptr>
+__device__ __forceinline__ void load_lines(float2 (&v)[PER][R], Ptr a, const LineInfo* info, int tid) {
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    int i = 0, l = 0;
+    const bool ok = bvalid<Tile, R>(q, tid);
+    if (ok) Tile::template bf<R>(tid + q * Tile::NT, i, l);
+    const LineInfo& li = info[l];
+    const int64_t base = (ok && li.valid) ? li.gbase + i : i;
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[q][m] = a[base + m * (N / R)];
+  }
+}
+
+// z edge values of this thread's elements to LDS (first t to zlo, last t to zhi)
+template <class Tile, int N, int R, int PER, int TM>
+__device__ __forceinline__ void put_z_edges(const float2 (&v)[PER][R], float2 (*zlo)[TM],
+                                            float2 (*zhi)[TM], const LineInfo* info, int t, int tid) {
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if (!bvalid<Tile, R>(q, tid)) continue;
+    int i, l;
+    Tile::template bf<R>(tid + q * Tile::NT, i, l);
+    if (!info[l].valid) continue;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int j = i + m * (N / R);
+      if (j < t) zlo[l][j] = v[q][m];
+      if (j >= N - t) zhi[l][j - (N - t)] = v[q][m];
+    }
+  }
+}
+
+// z edge term of element j of segment-line l (zero away from the edges)
+template <int N, int TM>
+__device__ __forceinline__ float2 z_edge_at(const float2 (*ez)[2 * TM], int l, int j, int t) {
+  if (j < t) return ez[l][j];
+  if (j >= N - t) return ez[l][j - (N - 2 * t)];
+  return make_float2(0.f, 0.f);
+}
+
+template <int N, bool SLAB_ONLY>
+__global__ __launch_bounds__(kThreads) void k_wpass(const SlotDesc* __restrict__ tab, Geo g, Tables tb) {
+  const SlotDesc& sd = tab[blockIdx.y];
+  if (sd.st->done != kRunning) return;
+  constexpr int L = lines_per_wg_c(N);
+  using Tile = LineTile<N, L>;
+  constexpr int P = plan_len(N);
+  constexpr int R0 = plan_radix(N, 0, false), RL = plan_radix(N, P - 1, false);
+  constexpr int PER0 = per_thread<Tile, R0>(), PERL = per_thread<Tile, RL>();
+  __shared__ float2 lds[Tile::LDS];
+  __shared__ LineInfo info[L];
+  constexpr int TM = kMaxT < N / 2 ? kMaxT : N / 2;  // t <= min(kMaxT, N / 2)
+  __shared__ float2 zlo[L][TM], zhi[L][TM], ez[L][2 * TM];
+  __shared__ float2 s_tw[N];
+  __shared__ float s_C[kMaxT * kMaxT];
+  const int tid = threadIdx.x;
+  global_lines<L, SLAB_ONLY>(g, sd, info, tid);
+  load_line_tables<N>(s_tw, s_C, tb, g, tid);
+  __syncthreads();
+  const int t = g.t;
+  const bool zc = g.a[2] > 0;
+  const float cim = sd.c_im;
+  const auto E0 = gp(sd.slab[0][2]);
+  const auto E1 = gp(sd.slab[1][2]);
+  const auto Y = gp(sd.ybox);
+  const auto W = gp(sd.W);
+  float2 xv[PER0][R0], bv[PER0][R0];
+  load_lines<Tile, N, R0, PER0>(xv, gp(sd.x), info, tid);
+  load_lines<Tile, N, R0, PER0>(bv, gp(sd.B), info, tid);
+  if (zc) {
+    put_z_edges<Tile, N, R0, PER0, TM>(xv, zlo, zhi, info, t, tid);
+    __syncthreads();
+    z_edge_terms<L, TM>(zlo, zhi, ez, info, g, s_C, cim, tid);
+    __syncthreads();
+  }
+  float2 v[PER0][R0];
+#pragma unroll
+  for (int q = 0; q < PER0; ++q) {
+    int i = 0, l = 0;
+    const bool ok = bvalid<Tile, R0>(q, tid);
+    if (ok) Tile::template bf<R0>(tid + q * Tile::NT, i, l);
+    const LineInfo& li = info[l];
+#pragma unroll
+    for (int m = 0; m < R0; ++m) {
+      const int j = i + m * (N / R0);
+      float2 w = make_float2(0.f, 0.f);
+      if (ok && li.valid) {
+        float2 e = make_float2(0.f, 0.f);
+        if (j >= li.jlo && j < li.jhi) e = Y[li.ybase + j];
+        if (li.e0 >= 0) e = cadd(e, E0[li.e0 + j]);
+        if (li.e1 >= 0) e = cadd(e, E1[li.e1 + j]);
+        if (zc) e = cadd(e, z_edge_at<N, TM>(ez, l, j, t));
+        w = form_w(bv[q][m], xv[q][m], e);
+      }
+      v[q][m] = w;
+    }
+  }
+  float2 o[PERL][RL];
+  fft_tile<Tile, N, false, -1>(v, o, lds, s_tw, tid);
+#pragma unroll
+  for (int q = 0; q < PERL; ++q) {
+    if (!bvalid<Tile, RL>(q, tid)) continue;
+    int i, l;
+    Tile::template bf<RL>(tid + q * Tile::NT, i, l);
+    if (!info[l].valid) continue;
+#pragma unroll
+    for (int m = 0; m < RL; ++m) W[info[l].gbase + i + m * (N / RL)] = o[q][m];
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__ tab, Geo g, Tables tb) {
+  const SlotDesc& sd = tab[blockIdx.y];
+  if (sd.st->done != kRunning) return;
+  constexpr int L = lines_per_wg_c(N);
+  using Tile = LineTile<N, L>;
+  constexpr int P = plan_len(N);
+  // inverse with the reversed radix order ends in the forward plan's first radix, so the
+  // inverse outputs a thread holds are exactly the forward stage-0 inputs it needs
+  constexpr int RI = plan_radix(N, 0, true), R0 = plan_radix(N, 0, false), RL = plan_radix(N, P - 1, false);
+  constexpr int PI = per_thread<Tile, RI>(), PER0 = per_thread<Tile, R0>(), PERL = per_thread<Tile, RL>();
+  __shared__ float2 lds[Tile::LDS];
+  __shared__ LineInfo info[L];
+  constexpr int TM = kMaxT < N / 2 ? kMaxT : N / 2;  // t <= min(kMaxT, N / 2)
+  __shared__ float2 zlo[L][TM], zhi[L][TM], ez[L][2 * TM];
+  __shared__ float2 s_tw[N];
+  __shared__ float s_C[kMaxT * kMaxT];
+  __shared__ double red[kThreads / 64];
+  __shared__ int any_plain;
+  const int tid = threadIdx.x;
+  global_lines<L, false>(g, sd, info, tid);
+  load_line_tables<N>(s_tw, s_C, tb, g, tid);
+  if (tid == 0) any_plain = 0;
+  __syncthreads();
+  const int t = g.t;
+  const bool zc = g.a[2] > 0;
+  const float cim = sd.c_im, alpha = sd.alpha;
+  const auto X = gp(sd.x);
+  const auto W = gp(sd.W);
+  // every global read of the tile is issued here: v of iteration n, x_n and B
+  float2 vin[PI][RI], xv[PER0][R0], bv[PER0][R0];
+  load_lines<Tile, N, RI, PI>(vin, W, info, tid);
+  load_lines<Tile, N, R0, PER0>(xv, X, info, tid);
+  load_lines<Tile, N, R0, PER0>(bv, gp(sd.B), info, tid);
+  float2 u[PER0][R0];
+  fft_tile<Tile, N, true, +1>(vin, u, lds, s_tw, tid);
+  // u = x - v; the z edge terms of u
+#pragma unroll
+  for (int q = 0; q < PER0; ++q)
+#pragma unroll
+    for (int m = 0; m < R0; ++m) u[q][m] = csub(xv[q][m], u[q][m]);
+  if (zc) {
+    put_z_edges<Tile, N, R0, PER0, TM>(u, zlo, zhi, info, t, tid);
+    __syncthreads();
+    z_edge_terms<L, TM>(zlo, zhi, ez, info, g, s_C, cim, tid);
+    __syncthreads();
+  }
+  const auto U0 = gp(sd.slab[0][1]);
+  const auto U1 = gp(sd.slab[1][1]);
+  double acc = 0.0;
+  bool plain_here = false;
+#pragma unroll
+  for (int q = 0; q < PER0; ++q) {
+    int i = 0, l = 0;
+    const bool ok = bvalid<Tile, R0>(q, tid);
+    if (ok) Tile::template bf<R0>(tid + q * Tile::NT, i, l);
+    const LineInfo& li = info[l];
+    if (!(ok && li.valid)) continue;
+    const bool slab = li.e0 >= 0 || li.e1 >= 0;
+#pragma unroll
+    for (int m = 0; m < R0; ++m) {
+      const int j = i + m * (N / R0);
+      const int64_t gi = li.gbase + j;
+      float2 d = cmul(bv[q][m], u[q][m]);
+      if (zc) d = cadd(d, z_edge_at<N, TM>(ez, l, j, t));
+      const float2 xn = make_float2(xv[q][m].x - alpha * d.x, xv[q][m].y - alpha * d.y);
+      X[gi] = xn;
+      if (slab) {
+        // x/y edge-slab line: its x/y corrections come later (k_slabA); keep the partial d in W
+        W[gi] = d;
+        if (li.e0 >= 0) U0[li.e0 + j] = u[q][m];
+        if (li.e1 >= 0) U1[li.e1 + j] = u[q][m];
+      } else {
+        acc += (double)d.x * d.x + (double)d.y * d.y;
+      }
+      xv[q][m] = xn;
+    }
+    plain_here |= !slab;
+  }
+  if (plain_here) any_plain = 1;
+  __syncthreads();
+  // next iteration's w on the lines that are complete
+  if (any_plain) {
+    const auto Y = gp(sd.ybox);
+    if (zc) {
+      put_z_edges<Tile, N, R0, PER0, TM>(xv, zlo, zhi, info, t, tid);
+      __syncthreads();
+      z_edge_terms<L, TM>(zlo, zhi, ez, info, g, s_C, cim, tid);
+      __syncthreads();
+    }
+    float2 v[PER0][R0];
+#pragma unroll
+    for (int q = 0; q < PER0; ++q) {
+      int i = 0, l = 0;
+      const bool ok = bvalid<Tile, R0>(q, tid);
+      if (ok) Tile::template bf<R0>(tid + q * Tile::NT, i, l);
+      const LineInfo& li = info[l];
+      const bool plain = ok && li.valid && li.e0 < 0 && li.e1 < 0;
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int j = i + m * (N / R0);
+        float2 w = make_float2(0.f, 0.f);
+        if (plain) {
+          float2 e = make_float2(0.f, 0.f);
+          if (j >= li.jlo && j < li.jhi) e = Y[li.ybase + j];
+          if (zc) e = cadd(e, z_edge_at<N, TM>(ez, l, j, t));
+          w = form_w(bv[q][m], xv[q][m], e);
+        }
+        v[q][m] = w;
+      }
+    }
+    float2 o[PERL][RL];
+    fft_tile<Tile, N, false, -1>(v, o, lds, s_tw, tid);
+#pragma unroll
+    for (int q = 0; q < PERL; ++q) {
+      if (!bvalid<Tile, RL>(q, tid)) continue;
+      int i, l;
+      Tile::template bf<RL>(tid + q * Tile::NT, i, l);
+      const LineInfo& li = info[l];
+      if (!li.valid || li.e0 >= 0 || li.e1 >= 0) continue;
+#pragma unroll
+      for (int m = 0; m < RL; ++m) W[li.gbase + i + m * (N / RL)] = o[q][m];
+    }
+  }
+  const double ssum = block_sum(acc, red);
+  if (tid == 0) gp(sd.part_main)[blockIdx.x] = ssum;
+}
+
+// finish the x/y edge-slab lines: d = d_partial + Eu_0 + Eu_1, x -= alpha (Eu_0 + Eu_1),
+// edge slabs X_0 / X_1 of the new iterate, residual partial sums
+__global__ __launch_bounds__(kThreads) void k_slabA(const SlotDesc* __restrict__ tab, Geo g) {
+  const SlotDesc& sd = tab[blockIdx.y];
+  if (sd.st->done != kRunning) return;
+  __shared__ double red[kThreads / 64];
+  const int per_col = slab_line_count(g);
+  const int n2 = g.n[2], t = g.t;
+  const int64_t per_sub = (int64_t)per_col * n2;
+  const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double acc = 0.0;
+  if (gid < (int64_t)g.S * per_sub) {
+    const int s = (int)(gid / per_sub);
+    const int64_t r = gid - (int64_t)s * per_sub;
+    const int k = (int)(r / n2);
+    const int j = (int)(r - (int64_t)k * n2);
+    int i0, i1;
+    slab_line_coords(k, g, i0, i1);
+    const int64_t gi = (((int64_t)s * g.n[0] + i0) * g.n[1] + i1) * n2 + j;
+    float2 esum = make_float2(0.f, 0.f);
+    int64_t a0 = -1, a1 = -1;
+    if (g.a[0] && (i0 < t || i0 >= g.n[0] - t)) {
+      const int side = i0 < t ? 0 : 1, aa = side ? i0 - (g.n[0] - t) : i0;
+      a0 = (((int64_t)s * 2 + side) * t + aa) * ((int64_t)g.n[1] * n2) + (int64_t)i1 * n2 + j;
+      esum = cadd(esum, gp(sd.slab[0][3])[a0]);
+    }
+    if (g.a[1] && (i1 < t || i1 >= g.n[1] - t)) {
+      const int side = i1 < t ? 0 : 1, aa = side ? i1 - (g.n[1] - t) : i1;
+      a1 = (((int64_t)s * 2 + side) * t + aa) * ((int64_t)g.n[0] * n2) + (int64_t)i0 * n2 + j;
+      esum = cadd(esum, gp(sd.slab[1][3])[a1]);
+    }
+    const float2 d = cadd(gp(sd.W)[gi], esum);
+    const float2 xv = gp(sd.x)[gi];
+    const float2 xn = make_float2(xv.x - sd.alpha * esum.x, xv.y - sd.alpha * esum.y);
+    gp(sd.x)[gi] = xn;
+    if (a0 >= 0) gp(sd.slab[0][0])[a0] = xn;
+    if (a1 >= 0) gp(sd.slab[1][0])[a1] = xn;
+    acc = (double)d.x * d.x + (double)d.y * d.y;
+  }
+  const double ssum = block_sum(acc, red);
+  if (threadIdx.x == 0) gp(sd.part_face)[blockIdx.x] = ssum;
+}
+
 // ---------------------------------------------------------------------------
 // edge corrections along one axis: for each line, from the first t (l) and
 // last t (h) values of the subdomain and its neighbours,
@@ -1271,9 +1683,9 @@ hipError_t launch_green_pass(const SlotDesc* tab, int nslots, const Geo& g, cons
 }
 
 hipError_t launch_corr(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, int which,
-                       hipStream_t s) {
+                       hipStream_t s, int axis_mask) {
   for (int d = 0; d < 3; ++d) {
-    if (g.a[d] == 0) continue;
+    if (g.a[d] == 0 || !(axis_mask & (1 << d))) continue;
     const int64_t plane = d == 0 ? (int64_t)g.n[1] * g.n[2]
                                  : (d == 1 ? (int64_t)g.n[0] * g.n[2] : (int64_t)g.n[0] * g.n[1]);
     const int64_t lines = (int64_t)g.S * plane;
@@ -1291,6 +1703,59 @@ hipError_t launch_corr(const SlotDesc* tab, int nslots, const Geo& g, const Tabl
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+int host_slab_line_count(const Geo& g) {
+  const int in0 = g.a[0] ? g.n[0] - 2 * g.t : g.n[0];
+  const int in1 = g.a[1] ? g.n[1] - 2 * g.t : g.n[1];
+  return g.n[0] * g.n[1] - in0 * in1;
+}
+
+bool fusion_supported(const Geo& g) { return lines_per_wg_c(g.n[2]) % g.P[2] == 0; }
+
+int64_t slabA_blocks(const Geo& g) {
+  return ((int64_t)g.S * host_slab_line_count(g) * g.n[2] + kThreads - 1) / kThreads;
+}
+
+hipError_t launch_fused(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, hipStream_t s) {
+  dim3 grid((unsigned)last_pass_blocks(g), nslots);
+  switch (g.n[2]) {
+#define MBS_CASE(NN) \
+  case NN: hipLaunchKernelGGL(k_fused<NN>, grid, dim3(kThreads), 0, s, tab, g, tb); break;
+    MBS_FOR_EACH_N(MBS_CASE)
+#undef MBS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_wpass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, int slab_only,
+                        hipStream_t s) {
+  const int L = lines_per_wg_c(g.n[2]);
+  const int64_t per_col = slab_only ? host_slab_line_count(g) : (int64_t)g.n[0] * g.n[1];
+  const int64_t segs = (int64_t)g.P[0] * g.P[1] * per_col * g.P[2];
+  if (segs == 0) return hipSuccess;
+  dim3 grid((unsigned)((segs + L - 1) / L), nslots);
+  switch (g.n[2]) {
+#define MBS_CASE(NN)                                                                              \
+  case NN:                                                                                        \
+    if (slab_only) hipLaunchKernelGGL((k_wpass<NN, true>), grid, dim3(kThreads), 0, s, tab, g, tb);  \
+    else hipLaunchKernelGGL((k_wpass<NN, false>), grid, dim3(kThreads), 0, s, tab, g, tb);           \
+    break;
+    MBS_FOR_EACH_N(MBS_CASE)
+#undef MBS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_slabA(const SlotDesc* tab, int nslots, const Geo& g, hipStream_t s) {
+  const int64_t nb = slabA_blocks(g);
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slabA, dim3((unsigned)nb, nslots), dim3(kThreads), 0, s, tab, g);
+  return hipGetLastError();
 }
 
 hipError_t launch_face(const SlotDesc* tab, int nslots, const Geo& g, hipStream_t s) {

@@ -112,6 +112,8 @@ struct mbs_plan_s {
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
   int nslots = 0;
   bool corr = false;
+  bool fused = false;       // fused z passes (last inverse + next forward)
+  bool corr01 = false;     // x or y axis corrected
   double normC = 0;
   int check_every = 16;
   bool use_graph = true;
@@ -285,8 +287,8 @@ mbs_status push_desc(mbs_plan p, int i) {
   return MBS_OK;
 }
 
-// enqueue one iteration for the slots of `tab` (nslots entries)
-hipError_t enqueue_iteration(mbs_plan p, const SlotDesc* tab, int nslots, hipStream_t s) {
+// enqueue one iteration with separate first and last z passes (also used by residual probes)
+hipError_t enqueue_iteration_unfused(mbs_plan p, const SlotDesc* tab, int nslots, hipStream_t s) {
   const Geo& g = p->geo;
   auto rec = [&](int kind, bool start) {
     if (!p->timing) return;
@@ -336,6 +338,62 @@ hipError_t enqueue_iteration(mbs_plan p, const SlotDesc* tab, int nslots, hipStr
   }
   rec(kReduce, true);
   if ((e = launch_reduce(tab, nslots, g, p->n_main, p->corr ? p->n_face : 0, s)) != hipSuccess) return e;
+  rec(kReduce, false);
+  return hipSuccess;
+}
+
+// enqueue one iteration with the fused z pass: the forward z FFT of the next iteration is
+// produced by the same pass that finishes this one (W must already hold this iteration's
+// forward z transform: see start_solve)
+hipError_t enqueue_iteration(mbs_plan p, const SlotDesc* tab, int nslots, hipStream_t s) {
+  if (!p->fused) return enqueue_iteration_unfused(p, tab, nslots, s);
+  const Geo& g = p->geo;
+  auto rec = [&](int kind, bool start) {
+    if (!p->timing) return;
+    const int idx = p->tcount;
+    if (start) {
+      if ((size_t)(2 * idx + 1) >= p->tev.size()) {
+        const size_t old = p->tev.size();
+        p->tev.resize(old + 64);
+        p->tkind.resize(p->tev.size() / 2);
+        for (size_t k = old; k < p->tev.size(); ++k) (void)hipEventCreate(&p->tev[k]);
+      }
+      p->tkind[idx] = kind;
+      (void)hipEventRecord(p->tev[2 * idx], s);
+    } else {
+      (void)hipEventRecord(p->tev[2 * idx + 1], s);
+      p->tcount++;
+    }
+  };
+  hipError_t e;
+  rec(kMidF, true);
+  if ((e = launch_mid_pass(tab, nslots, g, p->tb, 0, s)) != hipSuccess) return e;
+  rec(kMidF, false);
+  rec(kGreen, true);
+  if ((e = launch_green_pass(tab, nslots, g, p->tb, s)) != hipSuccess) return e;
+  rec(kGreen, false);
+  rec(kMidI, true);
+  if ((e = launch_mid_pass(tab, nslots, g, p->tb, 1, s)) != hipSuccess) return e;
+  rec(kMidI, false);
+  rec(kLast, true);
+  if ((e = launch_fused(tab, nslots, g, p->tb, s)) != hipSuccess) return e;
+  rec(kLast, false);
+  if (p->corr01) {
+    rec(kCorr, true);
+    if ((e = launch_corr(tab, nslots, g, p->tb, 1, s, 3)) != hipSuccess) return e;
+    rec(kCorr, false);
+    rec(kFace, true);
+    if ((e = launch_slabA(tab, nslots, g, s)) != hipSuccess) return e;
+    rec(kFace, false);
+    rec(kCorr, true);
+    if ((e = launch_corr(tab, nslots, g, p->tb, 0, s, 3)) != hipSuccess) return e;
+    rec(kCorr, false);
+    rec(kFirst, true);
+    if ((e = launch_wpass(tab, nslots, g, p->tb, 1, s)) != hipSuccess) return e;
+    rec(kFirst, false);
+  }
+  rec(kReduce, true);
+  if ((e = launch_reduce(tab, nslots, g, p->n_main, p->corr01 ? slabA_blocks(g) : 0, s)) != hipSuccess) return e;
   rec(kReduce, false);
   return hipSuccess;
 }
@@ -520,7 +578,7 @@ mbs_status probe_norm(mbs_plan p, int slot, float2* xsrc, double* rho) {
   if (p->corr && xsrc != s.x) {
     HIP_TRY(launch_extract_slabs(p->d_probe_tab, 0, p->geo, 0, p->stream));
   }
-  HIP_TRY(enqueue_iteration(p, p->d_probe_tab, 1, p->stream));
+  HIP_TRY(enqueue_iteration_unfused(p, p->d_probe_tab, 1, p->stream));
   SlotState* hb = p->h_states + 2 * (p->nslots + 1) - 1;
   HIP_TRY(hipMemcpyAsync(hb, p->d_states + p->nslots, sizeof(SlotState), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
@@ -572,6 +630,12 @@ mbs_status start_solve(mbs_plan p, int slot, const void* src, double tol, int32_
   init.done = kRunning;
   init.probe = 0;
   HIP_TRY(put_state(p->d_states + slot, init, p->stream));
+  if (p->fused) {
+    // W of iteration 0 (forward z transform of w_0) for this slot only
+    const SlotDesc* one = p->d_tab + slot;
+    if (p->corr01) HIP_TRY(launch_corr(one, 1, p->geo, p->tb, 0, p->stream, 3));
+    HIP_TRY(launch_wpass(one, 1, p->geo, p->tb, 0, p->stream));
+  }
   s.busy = true;
   s.start_seq = p->chunk_seq;
   s.finishing = false;
@@ -664,6 +728,8 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
   p->stream = (hipStream_t)hip_stream;
   p->nslots = desc->max_batch;
   p->corr = g.a[0] || g.a[1] || g.a[2];
+  p->corr01 = g.a[0] || g.a[1];
+  p->fused = !(desc->flags & MBS_NO_FUSION) && fusion_supported(g);
   p->check_every = desc->check_every > 0 ? desc->check_every : 16;
   p->timing = (desc->flags & MBS_TIMING) != 0;
   p->use_graph = !(desc->flags & (MBS_NO_GRAPH | MBS_TIMING));

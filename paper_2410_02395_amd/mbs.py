@@ -39,6 +39,7 @@ MBS_KB_FROM_K0 = 0x1
 MBS_X0_GIVEN = 0x2
 MBS_NO_GRAPH = 0x4
 MBS_TIMING = 0x8
+MBS_NO_FUSION = 0x10
 
 KERNEL_KINDS = ("first_z", "mid_y_fwd", "green_x", "mid_y_inv", "last_z", "edge_corr", "face", "reduce")
 

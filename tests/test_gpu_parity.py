@@ -17,8 +17,8 @@ pytestmark = pytest.mark.gpu
 TOL = 2e-5
 
 
-def _compare(shape, split, periodic, t, n, S, k_vac, rw, rm, iters, tol_bar=TOL):
-    x_gpu, res, hist = gpu_solve(shape, split, periodic, t, n, S, k_vac, rw, rm, 0.0, iters)
+def _compare(shape, split, periodic, t, n, S, k_vac, rw, rm, iters, tol_bar=TOL, flags=0):
+    x_gpu, res, hist = gpu_solve(shape, split, periodic, t, n, S, k_vac, rw, rm, 0.0, iters, flags=flags)
     pr = oracle_problem(shape, split, periodic, t, n, k_vac, rw, rm)
     ref = pr.solve(S, tol=0.0, max_iter=iters)
     print(f"shape={shape} split={split} periodic={periodic} t={t} iters={iters}", flush=True)
@@ -35,7 +35,7 @@ def _compare(shape, split, periodic, t, n, S, k_vac, rw, rm, iters, tol_bar=TOL)
     h = np.asarray(hist)
     e = np.asarray(ref.eps)
     assert np.max(np.abs(h - e) / e) < 1e-3
-    return err
+    return x_gpu
 
 
 def test_plain_sphere_64_fixed_iterations():
@@ -89,6 +89,25 @@ def test_decomposed_fixed_iterations(shape, split, periodic, t):
     n, S = random_case(shape, seed=7)
     k = 2 * math.pi / 4
     _compare(shape, split, periodic, t, n, S, k, (4, 4, 4), 0.2, 60)
+
+
+@pytest.mark.parametrize("shape,split,periodic,t", [
+    ((64, 64, 64), (2, 2, 2), (0, 0, 0), 8),
+    ((48, 24, 96), (2, 1, 2), (1, 0, 0), 4),
+    ((16, 24, 144), (1, 1, 3), (1, 1, 1), 4),    # three segments on a cyclic z axis
+])
+def test_separate_and_fused_z_passes_agree(shape, split, periodic, t):
+    """The two launch sequences (the inverse z pass of one iteration fused with the
+    forward z pass of the next, or kept apart) both meet the bar and differ only by
+    rounding order."""
+    from paper_2410_02395_amd import mbs
+    n, S = random_case(shape, seed=9)
+    k = 2 * math.pi / 4
+    fused = _compare(shape, split, periodic, t, n, S, k, (4, 4, 4), 0.2, 50)
+    apart = _compare(shape, split, periodic, t, n, S, k, (4, 4, 4), 0.2, 50, flags=mbs.MBS_NO_FUSION)
+    d = rel_l2(fused, apart)
+    print(f"  fused vs separate: rel L2 {d:.3e}", flush=True)
+    assert d <= 1e-5
 
 
 @pytest.mark.parametrize("shape", [(8, 8, 8), (16, 12, 24), (96, 32, 64), (12, 192, 8)])
