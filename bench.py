@@ -25,14 +25,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE on the dd1024 workload, scaled by
-# the same counters on a plain 2 GiB copy (FETCH factor 0.5, WRITE factor 1.0).  Valid only for
-# the kernel source they were taken on; any other source reports traffic = null.
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE on the dd1024 workload with the fused
+# z pass, scaled by the same counters on a plain 2 GiB copy (FETCH factor 0.5, WRITE factor 1.0).
+# Valid only for the kernel source they were taken on; any other source reports traffic = null.
 PMC_TRAFFIC = {
     "workload": "dd1024",
-    "kernel_source_sha256": "8b0f82b50d5d2bac8cfb362e4d708c8c935f6cc117211588534da539341e2aff",
-    "bytes": {"first_z": 27.414e9, "mid_y_fwd": 17.180e9, "green_x": 17.182e9, "mid_y_inv": 17.180e9,
-              "last_z": 35.185e9, "face": 5.995e9, "edge_corr": 0.671e9},
+    "fused": True,
+    "kernel_source_sha256": "9e3ef10a5c0de0d8ae6abf9f9b7e42a9071c086eb28c7b5fe5ee4d068ce90447",
+    "bytes": {"z_fwd": 2.137e9, "y_fwd": 17.180e9, "x_green": 17.180e9, "y_inv": 17.180e9,
+              "z_inv": 43.567e9, "edge_corr": 1.342e9, "face": 3.097e9},
 }
 METRIC = "MBS voxel-updates/s + HBM GB/s at 1024³; served solves/s and p99 latency"
 
@@ -68,26 +69,28 @@ def algorithmic_bytes(shape, split, periodic, t, src_box, fused=True):
         SLV = S * (n[0] * n[1] - in0 * in1) * n[2]
         slabs01 = sum(slab_elems(n, S, t, a, d) for d in range(2))
         return {
-            # w-pass on the x/y edge-slab lines: read x, B, Ex_0/Ex_1; write W
-            "first_z": 24 * SLV + 8 * slabs01 + 8 * src_box,
-            "mid_y_fwd": 16 * V,
-            "green_x": 16 * V,
-            "mid_y_inv": 16 * V,
-            # fused z pass: read W, x, B; write x, W (d on edge lines), U slabs
-            "last_z": 40 * V + 8 * slabs01 + 8 * n_main,
-            "edge_corr": 16 * slabs01 // 2 if slabs01 else 0,
-            # read d, x, Eu; write x, X slabs
-            "face": 8 * (3 * SLV + slabs01) + 8 * ((SLV + 255) // 256),
+            # w pass on the x/y edge-slab lines: read x, B, Ex_0/Ex_1; write W
+            "z_fwd": 24 * SLV + 8 * slabs01,
+            "y_fwd": 16 * V,
+            "x_green": 16 * V,
+            "y_inv": 16 * V,
+            # fused z pass: read W, x, B (+ source box); write x, W (d on edge-slab lines),
+            # the u values of the x/y edge slabs, partial sums
+            "z_inv": 40 * V + 8 * src_box + 8 * slabs01 + 8 * n_main,
+            # one record covers axes 0 and 1: read the slab values, write the corrections
+            "edge_corr": 16 * slabs01,
+            # edge-slab lines: read d, x, Eu_0/Eu_1; write x and the iterate's X_0/X_1 slabs
+            "face": 24 * SLV + 16 * slabs01 + 8 * ((SLV + 255) // 256),
             "reduce": 8 * (n_main + (SLV + 255) // 256),
         }
     return {
         # read x, B (+ edge corrections, source box), write W
-        "first_z": 24 * V + 8 * slabs + 8 * src_box,
-        "mid_y_fwd": 16 * V,
-        "green_x": 16 * V,
-        "mid_y_inv": 16 * V,
+        "z_fwd": 24 * V + 8 * slabs + 8 * src_box,
+        "y_fwd": 16 * V,
+        "x_green": 16 * V,
+        "y_inv": 16 * V,
         # read W, x, B, write x (+ edge slabs of u, partial sums)
-        "last_z": 32 * V + 8 * slabs + 8 * n_main,
+        "z_inv": 32 * V + 8 * slabs + 8 * n_main,
         # per axis: read the slab values, write the corrections
         "edge_corr": 16 * slabs,
         # read corrections, u, B, x; write x and the iterate's edge slabs
@@ -96,7 +99,7 @@ def algorithmic_bytes(shape, split, periodic, t, src_box, fused=True):
     }
 
 
-def cpu_baseline(n_dev, S_dev, w, iters=3, edge=256):
+def cpu_baseline(n_dev, S_dev, w, iters=16, edge=256):
     """Time the FP64 oracle on a bounded sample: the first edge^3 block of the
     workload's medium and source, decomposed like the workload."""
     import numpy as np
@@ -274,7 +277,8 @@ def main():
     src = os.path.join(ROOT, "paper_2410_02395_amd", "csrc", "mbs_kernels.hip")
     with open(src, "rb") as fh:
         digest = hashlib.sha256(fh.read()).hexdigest()
-    if w.name == PMC_TRAFFIC["workload"] and digest == PMC_TRAFFIC["kernel_source_sha256"]:
+    if (w.name == PMC_TRAFFIC["workload"] and digest == PMC_TRAFFIC["kernel_source_sha256"]
+            and PMC_TRAFFIC["fused"] == (not args.no_fusion)):
         traffic = PMC_TRAFFIC["bytes"].get(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

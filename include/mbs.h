@@ -137,9 +137,11 @@ mbs_status mbs_residual_history(mbs_plan plan, int32_t slot, double* host_out, i
 
 /* Kernel timing (plans created with MBS_TIMING): per kernel kind, the summed HIP-event
  * duration in ms and the launch count since the last reset.  Kinds, in order:
- * 0 first forward pass (z), 1 forward pass (y), 2 Green pass (x), 3 inverse pass (y),
- * 4 last inverse pass with update (z), 5 edge corrections, 6 face update, 7 residual
- * reduction.  n_kinds <= 8. */
+ * 0 forward pass (z), 1 forward pass (y), 2 Green pass (x), 3 inverse pass (y),
+ * 4 inverse pass with update (z), 5 edge corrections, 6 face update, 7 residual
+ * reduction.  With the fused z pass, kind 4 also forms the next w and its forward z FFT,
+ * kind 0 covers only the lines of the x/y edge slabs and kind 6 finishes those lines.
+ * n_kinds <= 8. */
 mbs_status mbs_timing_read(mbs_plan plan, double* ms, int64_t* launches, int32_t n_kinds,
                            int32_t reset);
 

@@ -41,7 +41,10 @@ MBS_NO_GRAPH = 0x4
 MBS_TIMING = 0x8
 MBS_NO_FUSION = 0x10
 
-KERNEL_KINDS = ("first_z", "mid_y_fwd", "green_x", "mid_y_inv", "last_z", "edge_corr", "face", "reduce")
+# kernel kinds of mbs_timing_read, in order (with the fused z pass, "z_fwd" covers only the
+# x/y edge-slab lines, "z_inv" also forms and transforms the next w, "face" finishes the
+# edge-slab lines)
+KERNEL_KINDS = ("z_fwd", "y_fwd", "x_green", "y_inv", "z_inv", "edge_corr", "face", "reduce")
 
 
 class PlanDesc(ctypes.Structure):
