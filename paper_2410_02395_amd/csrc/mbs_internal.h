@@ -86,11 +86,11 @@ struct Tables {
 };
 
 int lines_per_wg(int n);   // contiguous passes: lines per workgroup
-int cols_per_tile(int n);  // strided passes: columns (z) per tile
 bool fft_size_supported(int n);
 
 hipError_t launch_first_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
                              hipStream_t s);
+void prepare_launches(const Geo& g);
 hipError_t launch_mid_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
                            int inverse, hipStream_t s);
 hipError_t launch_green_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,

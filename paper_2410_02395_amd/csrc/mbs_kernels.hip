@@ -204,11 +204,35 @@ __host__ __device__ constexpr int col_threads_c(int n) { return n >= 384 ? 512 :
 #define MBS_COL_WAVES_BIG 2
 #endif
 __host__ __device__ constexpr int col_waves_c(int n) { return col_threads_c(n) == 512 ? MBS_COL_WAVES_BIG : 2; }
+// 1: the next tile's loads are issued before the current tile's FFT stages
+#ifndef MBS_COL_PREFETCH
+#define MBS_COL_PREFETCH 1
+#endif
+// tile shape of the x pass (two FFTs per column) for 384 <= N <= 512
+#ifndef MBS_GREEN_WC
+#define MBS_GREEN_WC 16
+#endif
+#ifndef MBS_GREEN_NT
+#define MBS_GREEN_NT 1024
+#endif
+#ifndef MBS_GREEN_WAVES
+#define MBS_GREEN_WAVES 4
+#endif
+// per pass kind: columns per tile, threads per workgroup, minimum waves per SIMD
+__host__ __device__ constexpr int col_wc_c(int n, int kind) {
+  return (kind == 2 && n >= 384 && n <= 512) ? MBS_GREEN_WC : cols_per_tile_c(n);
+}
+__host__ __device__ constexpr int col_nt_c(int n, int kind) {
+  return (kind == 2 && n >= 384 && n <= 512) ? MBS_GREEN_NT : col_threads_c(n);
+}
+__host__ __device__ constexpr int col_wv_c(int n, int kind) {
+  return (kind == 2 && n >= 384 && n <= 512) ? MBS_GREEN_WAVES : col_waves_c(n);
+}
 
-// N rows (the FFT axis) x WC contiguous columns; element (j, c) at j*WC + c.
-template <int N, int WC>
+// N rows (the FFT axis) x WC contiguous columns, NTH threads; element (j, c) at j*WC + c.
+template <int N, int WC, int NTH>
 struct ColTile {
-  static constexpr int NT = col_threads_c(N);
+  static constexpr int NT = NTH;
   static constexpr int ELEMS = N * WC;
   static constexpr int LDS = ELEMS;
   __device__ __forceinline__ static int idx(int j, int c) { return j * WC + c; }
@@ -567,10 +591,9 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
 // Persistent workgroups walk the tiles; the loads of the next tile are issued
 // before the LDS stages of the current one so that HBM traffic and LDS work overlap.
 // ---------------------------------------------------------------------------
-template <int N, int WC, int R, int PER, bool FULL, class Ptr>
+template <class Tile, int N, int R, int PER, bool FULL, class Ptr>
 __device__ __forceinline__ void load_cols(float2 (&v)[PER][R], Ptr tp, int stride, int ncols, int tid) {
   // tp: first element of the tile (uniform); per-lane offsets are 32-bit
-  using Tile = ColTile<N, WC>;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const bool ok = bvalid<Tile, R>(q, tid);
@@ -593,8 +616,8 @@ template <int N, int KIND, bool FULL, class Ptr>
 __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, int64_t tile, int64_t ntiles,
                                          float2* lds, const float2* s_tw, const float* s_p2x, const float* s_p2y,
                                          const float* s_p2z, float kb2, float cim, float inv) {
-  constexpr int WC = cols_per_tile_c(N);
-  using Tile = ColTile<N, WC>;
+  constexpr int WC = col_wc_c(N, KIND);
+  using Tile = ColTile<N, WC, col_nt_c(N, KIND)>;
   constexpr int P = plan_len(N);
   constexpr int R0 = plan_radix(N, 0, false), RL = plan_radix(N, P - 1, false);
   constexpr int PER0 = per_thread<Tile, R0>(), PERL = per_thread<Tile, RL>();
@@ -614,7 +637,7 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
   int c0 = cb * WC, ncols = min(WC, n2 - c0);
   int64_t base = tile_base(sub, fix, cb);
   float2 cur[PER0][R0];
-  load_cols<N, WC, R0, PER0, FULL>(cur, W + base, stride, ncols, tid);
+  load_cols<Tile, N, R0, PER0, FULL>(cur, W + base, stride, ncols, tid);
   fft_head<Tile, N, false, KIND == 1 ? +1 : -1, PER0, R0>(cur, lds, s_tw, tid);
   // output registers of the previous tile (the FFT result that is stored)
   constexpr int PERO = KIND == 2 ? PER0 : PERL;
@@ -633,7 +656,7 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
     const int nc0 = ncb * WC, nncols = min(WC, n2 - nc0);
     const int64_t nbase = tile_base(nsub, nfx, ncb);
     float2 nxt[PER0][R0];
-    if (more) load_cols<N, WC, R0, PER0, FULL>(nxt, W + nbase, stride, nncols, tid);
+    if (MBS_COL_PREFETCH && more) load_cols<Tile, N, R0, PER0, FULL>(nxt, W + nbase, stride, nncols, tid);
     keep_alive(o);
     if constexpr (KIND == 2) {
       float2 f[PERL][RL];
@@ -670,6 +693,7 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
       for (int m = 0; m < RO; ++m) tp[o0 + m * (N / RO) * stride] = o[q][m];
     }
     if (!more) break;
+    if (!MBS_COL_PREFETCH) load_cols<Tile, N, R0, PER0, FULL>(nxt, W + nbase, stride, nncols, tid);
     fft_head<Tile, N, false, KIND == 1 ? +1 : -1, PER0, R0>(nxt, lds, s_tw, tid);
 #pragma unroll
     for (int q = 0; q < PER0; ++q)
@@ -686,14 +710,14 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
 }
 
 template <int N, int KIND>
-__global__ __launch_bounds__(col_threads_c(N), col_waves_c(N)) void k_col(const SlotDesc* __restrict__ tab, Geo g, Tables tb,
-                                                      int64_t ntiles) {
+__global__ __launch_bounds__(col_nt_c(N, KIND), col_wv_c(N, KIND)) void k_col(const SlotDesc* __restrict__ tab, Geo g,
+                                                                            Tables tb, int64_t ntiles) {
   const SlotDesc& sd = tab[blockIdx.y];
   if (sd.st->done != kRunning) return;
   int64_t tile = blockIdx.x;
   if (tile >= ntiles) return;
-  constexpr int WC = cols_per_tile_c(N);
-  using Tile = ColTile<N, WC>;
+  constexpr int WC = col_wc_c(N, KIND);
+  using Tile = ColTile<N, WC, col_nt_c(N, KIND)>;
   constexpr int P = plan_len(N);
   constexpr int R0 = plan_radix(N, 0, false), RL = plan_radix(N, P - 1, false);
   constexpr int PER0 = per_thread<Tile, R0>(), PERL = per_thread<Tile, RL>();
@@ -1579,7 +1603,6 @@ hipError_t put_i32x8(int32_t* dst, const int32_t* v, hipStream_t s) {
 }
 
 int lines_per_wg(int n) { return lines_per_wg_c(n); }
-int cols_per_tile(int n) { return cols_per_tile_c(n); }
 
 #define MBS_FOR_EACH_N(X) \
   X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
@@ -1640,23 +1663,64 @@ hipError_t launch_last_pass(const SlotDesc* tab, int nslots, const Geo& g, const
   return hipGetLastError();
 }
 
-static inline unsigned persistent_grid(int64_t ntiles, const Geo& g, int threads) {
-  // two resident workgroups per compute unit (one for 512-thread tiles limited to 2 waves/SIMD)
-  const int per_cu = (threads == 512 && MBS_COL_WAVES_BIG < 4) ? 1 : 2;
+// workgroups of a column kernel resident per compute unit (registers and LDS), queried once
+template <int NN, int KIND>
+static int col_resident_per_cu() {
+  static const int v = [] {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_col<NN, KIND>),
+                                                     col_nt_c(NN, KIND), 0) != hipSuccess || nb < 1)
+      nb = 1;
+    return nb;
+  }();
+  return v;
+}
+
+// persistent grid: every resident workgroup slot of the device, at most one per tile
+static inline unsigned persistent_grid(int64_t ntiles, const Geo& g, int per_cu) {
   const int64_t cap = (int64_t)per_cu * (g.cus > 0 ? g.cus : 256);
   return (unsigned)(ntiles < cap ? ntiles : cap);
 }
 
+template <int NN, int KIND>
+static void launch_col(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, hipStream_t s) {
+  constexpr int WC = col_wc_c(NN, KIND);
+  const int fix = KIND == 2 ? g.n[1] : g.n[0];
+  const int64_t ntiles = (int64_t)g.S * fix * ((g.n[2] + WC - 1) / WC);
+  dim3 grid(persistent_grid(ntiles, g, col_resident_per_cu<NN, KIND>()), nslots);
+  hipLaunchKernelGGL((k_col<NN, KIND>), grid, dim3(col_nt_c(NN, KIND)), 0, s, tab, g, tb, ntiles);
+}
+
+// occupancy queries of the plan's column kernels, made before any stream capture
+void prepare_launches(const Geo& g) {
+  switch (g.n[1]) {
+#define MBS_CASE(NN)                 \
+  case NN:                           \
+    (void)col_resident_per_cu<NN, 0>(); \
+    (void)col_resident_per_cu<NN, 1>(); \
+    break;
+    MBS_FOR_EACH_N(MBS_CASE)
+#undef MBS_CASE
+    default:
+      break;
+  }
+  switch (g.n[0]) {
+#define MBS_CASE(NN) \
+  case NN: (void)col_resident_per_cu<NN, 2>(); break;
+    MBS_FOR_EACH_N(MBS_CASE)
+#undef MBS_CASE
+    default:
+      break;
+  }
+}
+
 hipError_t launch_mid_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
                            int inverse, hipStream_t s) {
-  const int WC = cols_per_tile_c(g.n[1]);
-  const int64_t ntiles = (int64_t)g.S * g.n[0] * ((g.n[2] + WC - 1) / WC);
-  dim3 grid(persistent_grid(ntiles, g, col_threads_c(g.n[1])), nslots);
   switch (g.n[1]) {
-#define MBS_CASE(NN)                                                                              \
-  case NN:                                                                                        \
-    if (inverse) hipLaunchKernelGGL((k_col<NN, 1>), grid, dim3(col_threads_c(NN)), 0, s, tab, g, tb, ntiles); \
-    else hipLaunchKernelGGL((k_col<NN, 0>), grid, dim3(col_threads_c(NN)), 0, s, tab, g, tb, ntiles);         \
+#define MBS_CASE(NN)                                          \
+  case NN:                                                    \
+    if (inverse) launch_col<NN, 1>(tab, nslots, g, tb, s);    \
+    else launch_col<NN, 0>(tab, nslots, g, tb, s);            \
     break;
     MBS_FOR_EACH_N(MBS_CASE)
 #undef MBS_CASE
@@ -1668,12 +1732,9 @@ hipError_t launch_mid_pass(const SlotDesc* tab, int nslots, const Geo& g, const 
 
 hipError_t launch_green_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
                              hipStream_t s) {
-  const int WC = cols_per_tile_c(g.n[0]);
-  const int64_t ntiles = (int64_t)g.S * g.n[1] * ((g.n[2] + WC - 1) / WC);
-  dim3 grid(persistent_grid(ntiles, g, col_threads_c(g.n[0])), nslots);
   switch (g.n[0]) {
 #define MBS_CASE(NN) \
-  case NN: hipLaunchKernelGGL((k_col<NN, 2>), grid, dim3(col_threads_c(NN)), 0, s, tab, g, tb, ntiles); break;
+  case NN: launch_col<NN, 2>(tab, nslots, g, tb, s); break;
     MBS_FOR_EACH_N(MBS_CASE)
 #undef MBS_CASE
     default:

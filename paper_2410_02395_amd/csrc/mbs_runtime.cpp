@@ -745,6 +745,7 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) return fail(MBS_EHIP);
     p->geo.cus = cus;
   }
+  prepare_launches(p->geo);
   if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(MBS_EHIP);
   if (hipEventCreateWithFlags(&p->chunk_ev, hipEventDisableTiming) != hipSuccess) return fail(MBS_EHIP);
   // tables: twiddles, |p|^2 per axis, correction block (FP64 on the host, rounded once)

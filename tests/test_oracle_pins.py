@@ -380,3 +380,55 @@ def test_dielectric_slab_matches_fabry_perot():
         assert abs(r * r + tau * tau - 1) < 2e-3
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 2e-2
+
+
+# ---------------------------------------------------------------------------
+# convergence studies of Sec. 4.2 (truncation parameter, number of subdomains)
+# ---------------------------------------------------------------------------
+def _line_case(N=192, seed=3):
+    """A 1D line (N, 1, 1) of a smoothed random medium, n in [1, 1.5] with a
+    small absorption, 6 points per wavelength, point source at N/3."""
+    from mbs_inputs import smoothed_random_medium
+    n = smoothed_random_medium((N, 1, 1), seed, 1.0, 1.5, 3.0) + np.complex64(0.02j)
+    S = np.zeros((N, 1, 1), np.complex64)
+    S[N // 3, 0, 0] = 1
+    return n.astype(np.complex64), S, 2 * math.pi / 6
+
+
+def test_truncation_error_decays_with_t_and_iterations_do_not_depend_on_t():
+    """Sec. 4.2.1 / Fig. 7: two subdomains on a cyclic axis against the single
+    periodic domain they decompose.  The error is the truncation of the
+    communication and wrap blocks alone; it falls with t (squared relative
+    error, the paper's measure, below 1e-3 from t = 4 on) while the iteration
+    count stays the same for t >= 4."""
+    n, S, k = _line_case()
+    N = n.shape[0]
+    ref = O.MBSProblem((N, 1, 1), (1, 1, 1), (1, 1, 1), 8, n, k).solve(S, tol=1e-10, max_iter=20000)
+    assert ref.converged
+    errs, iters = {}, {}
+    for t in (4, 8, 16, 24):
+        r = O.MBSProblem((N, 1, 1), (2, 1, 1), (1, 1, 1), t, n, k).solve(S, tol=1e-10, max_iter=20000)
+        assert r.converged
+        errs[t] = np.linalg.norm(r.x - ref.x) / np.linalg.norm(ref.x)
+        iters[t] = r.iterations
+    ts = sorted(errs)
+    assert all(errs[a] > errs[b] for a, b in zip(ts, ts[1:])), errs
+    assert errs[4] ** 2 < 1e-3 and errs[24] < 0.1 * errs[4], errs
+    assert max(iters.values()) <= 1.02 * min(iters.values()), iters
+
+
+def test_iterations_do_not_depend_on_the_number_of_subdomains():
+    """Sec. 4.2.2: splitting an axis into 2, 3 or 4 subdomains leaves c (Eq. 9,
+    a_d = 2 in every case) and the iteration count to a fixed tolerance the same
+    to within 5 %."""
+    n, S, k = _line_case()
+    N = n.shape[0]
+    its, cs = [], []
+    for P in (2, 3, 4):
+        pr = O.MBSProblem((N, 1, 1), (P, 1, 1), (1, 1, 1), 8, n, k)
+        r = pr.solve(S, tol=1e-6, max_iter=20000)
+        assert r.converged
+        its.append(r.iterations)
+        cs.append(pr.c)
+    assert cs[0] == cs[1] == cs[2]
+    assert max(its) <= 1.05 * min(its), its
