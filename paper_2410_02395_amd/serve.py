@@ -222,4 +222,7 @@ def summarize(reqs: List[Request]) -> dict:
         "p99_latency_s": pct(99),
         "converged": sum(1 for r in reqs if r.result and r.result["converged"]),
         "iterations_total": sum(r.result["iterations"] for r in reqs if r.result),
+        # voxel-updates of all solves per second of makespan (how busy the stream kept the GPU)
+        "voxel_updates_per_s": sum(r.shape[0] * r.shape[1] * r.shape[2] * r.result["iterations"]
+                                   for r in reqs if r.result) / makespan,
     }
