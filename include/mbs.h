@@ -72,6 +72,15 @@ typedef struct {
     double alpha;        /* relaxation, 0 < alpha <= 1 (0.75 in Eq. 4)                       */
     uint32_t flags;      /* MBS_* plan flags                                                 */
     int32_t check_every; /* iterations per graph launch between host checks; 0 = 16          */
+    double activation;   /* subdomain activation (Sec. 3.1, end); 0 = off.  > 0: a solve     */
+                         /* starts by iterating only the subdomains that hold source (all of */
+                         /* them with MBS_X0_GIVEN); every check_every iterations, a         */
+                         /* subdomain joins once the 2-norm of the edge terms its iterated   */
+                         /* neighbours transfer into it exceeds activation * ||Gamma^-1 y||. */
+                         /* Subdomains not iterated keep x = 0 and add nothing to the        */
+                         /* residual; a solve that converges on the iterated set goes on if  */
+                         /* some transfer still exceeds the threshold.  Needs the fused z    */
+                         /* pass and at most 4096 subdomains (else MBS_EUNSUPPORTED).        */
 } mbs_plan_desc;
 
 typedef struct {
@@ -91,6 +100,8 @@ typedef struct {
     double normC;        /* ||A12||_2 of the t x t correction block                          */
     double rho_ref;      /* ||Gamma^-1 y||                                                   */
     int32_t status;      /* MBS_OK, or the error that stopped the iteration                  */
+    int64_t subdomain_iterations; /* sum over iterations of the subdomains iterated: the     */
+                         /* iteration count times the subdomain count without activation   */
 } mbs_result;
 
 /* Device bytes a plan with this descriptor allocates (all slots), for HBM-budget admission

@@ -10,6 +10,8 @@ constexpr int kThreads = 256;       // threads per workgroup of every kernel (4 
 constexpr int kMaxT = 16;           // largest truncation t of the correction blocks
 constexpr int kHistCap = 1 << 16;   // residual history entries kept per slot
 constexpr int kReduceBlocks = 64;   // first-stage workgroups of the residual reduction
+constexpr int kXferBlocks = 32;     // partial sums per subdomain of the transfer norms
+constexpr int kMaxActSub = 4096;    // subdomains per plan when activation is on
 
 // stop reasons written by the residual kernel
 enum : int32_t {
@@ -74,7 +76,11 @@ struct SlotDesc {
   double* part_face;      // residual partials of the face update
   double* hist;           // relative residual per iteration
   double* part_red;       // first-stage sums of the residual reduction (kReduceBlocks)
-  int32_t active;
+  const uint32_t* act;    // bit s set: subdomain s is iterated (nullptr: every subdomain)
+  const int32_t* act_list;  // ids of the iterated subdomains, ascending (nullptr: all, in order)
+  double* xfer;           // [S][kXferBlocks] partial sums of the field transferred into
+                          // inactive subdomains (nullptr: activation off)
+  int32_t n_act;          // entries of act_list
   int32_t pad;
 };
 
@@ -91,6 +97,7 @@ bool fft_size_supported(int n);
 hipError_t launch_first_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
                              hipStream_t s);
 void prepare_launches(const Geo& g);
+hipError_t launch_xfer(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, hipStream_t s);
 hipError_t launch_mid_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
                            int inverse, hipStream_t s);
 hipError_t launch_green_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,

@@ -27,14 +27,25 @@ namespace mbs {
 // Pointers read from the slot table are generic; casting them to the global address
 // space makes the compiler emit global (not flat) loads and stores, which do not
 // count against the LDS wait counter and so stay in flight across LDS barriers.
+// Small tables that no kernel writes while it runs (the list of iterated subdomains) are read
+// through the constant address space instead: uniform reads then become scalar loads, which
+// do not count against the vector-memory wait counter of the streaming loops.
 #if defined(__HIP_DEVICE_COMPILE__)
 template <class T>
 __device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
   return (__attribute__((address_space(1))) T*)p;
 }
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* cp(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
 #else
 template <class T>
 __device__ __forceinline__ T* gp(T* p) {  // host pass: parsed only, never executed
+  return p;
+}
+template <class T>
+__device__ __forceinline__ const T* cp(const T* p) {
   return p;
 }
 #endif
@@ -393,19 +404,26 @@ struct LineInfo {
   int64_t ybase;   // source box index of element j (ybase + j), valid for j in [jlo, jhi)
   int32_t jlo, jhi;
   int32_t valid;
-  int32_t pad;
+  int32_t on;      // the line's subdomain is iterated (subdomain activation, Sec. 3.1)
 };
+
+// subdomain s is iterated (all are when no activation mask is set)
+__device__ __forceinline__ bool sub_on(const uint32_t* act, int s) {
+  return act == nullptr || ((act[s >> 5] >> (s & 31)) & 1u) != 0u;
+}
 
 __device__ __forceinline__ void line_info(int64_t line, const Geo& g, const SlotDesc& sd,
                                           LineInfo& li) {
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], t = g.t;
   const int64_t nlines = (int64_t)g.S * n0 * n1;
   li.valid = line < nlines;
+  li.on = 0;
   if (!li.valid) return;
   const int i1 = (int)(line % n1);
   const int64_t r = line / n1;
   const int i0 = (int)(r % n0);
   const int s = (int)(r / n0);
+  li.on = sub_on(sd.act, s) ? 1 : 0;
   li.gbase = line * n2;
   li.e0 = -1;
   li.e1 = -1;
@@ -615,7 +633,8 @@ __device__ __forceinline__ void load_cols(float2 (&v)[PER][R], Ptr tp, int strid
 template <int N, int KIND, bool FULL, class Ptr>
 __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, int64_t tile, int64_t ntiles,
                                          float2* lds, const float2* s_tw, const float* s_p2x, const float* s_p2y,
-                                         const float* s_p2z, float kb2, float cim, float inv) {
+                                         const float* s_p2z, float kb2, float cim, float inv,
+                                         const int32_t* act_list) {
   constexpr int WC = col_wc_c(N, KIND);
   using Tile = ColTile<N, WC, col_nt_c(N, KIND)>;
   constexpr int P = plan_len(N);
@@ -630,9 +649,12 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
   int cb = (int)(tile % CB), fix = (int)((tile / CB) % nfix), sub = (int)(tile / ((int64_t)CB * nfix));
   const int gcb = (int)(gridDim.x % CB), grest = (int)(gridDim.x / CB);
   const int gfix = grest % nfix, gsub = grest / nfix;
+  // the walk runs over the iterated subdomains only (subdomain activation, Sec. 3.1): entry
+  // s_ of the list, read with a scalar load so no vector load besides the tiles is in flight
   auto tile_base = [&](int s_, int fix_, int cb_) -> int64_t {
-    return KIND == 2 ? ((int64_t)s_ * N * n1 + fix_) * n2 + cb_ * WC
-                     : (((int64_t)s_ * n0 + fix_) * N) * n2 + cb_ * WC;
+    const int sid = act_list ? cp(act_list)[__builtin_amdgcn_readfirstlane(s_)] : s_;
+    return KIND == 2 ? ((int64_t)sid * N * n1 + fix_) * n2 + cb_ * WC
+                     : (((int64_t)sid * n0 + fix_) * N) * n2 + cb_ * WC;
   };
   int c0 = cb * WC, ncols = min(WC, n2 - c0);
   int64_t base = tile_base(sub, fix, cb);
@@ -654,7 +676,7 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
     if (ncb >= CB) { ncb -= CB; ++nfx; }
     if (nfx >= nfix) { nfx -= nfix; ++nsub; }
     const int nc0 = ncb * WC, nncols = min(WC, n2 - nc0);
-    const int64_t nbase = tile_base(nsub, nfx, ncb);
+    const int64_t nbase = more ? tile_base(nsub, nfx, ncb) : base;
     float2 nxt[PER0][R0];
     if (MBS_COL_PREFETCH && more) load_cols<Tile, N, R0, PER0, FULL>(nxt, W + nbase, stride, nncols, tid);
     keep_alive(o);
@@ -714,6 +736,7 @@ __global__ __launch_bounds__(col_nt_c(N, KIND), col_wv_c(N, KIND)) void k_col(co
                                                                             Tables tb, int64_t ntiles) {
   const SlotDesc& sd = tab[blockIdx.y];
   if (sd.st->done != kRunning) return;
+  if (sd.act_list) ntiles = ntiles / g.S * sd.n_act;  // tiles of the iterated subdomains only
   int64_t tile = blockIdx.x;
   if (tile >= ntiles) return;
   constexpr int WC = col_wc_c(N, KIND);
@@ -743,9 +766,9 @@ __global__ __launch_bounds__(col_nt_c(N, KIND), col_wv_c(N, KIND)) void k_col(co
   const auto W = gp(sd.W);
   const float kb2 = sd.kb2, cim = sd.c_im, inv = sd.inv_vox;
   if (n2 % WC == 0)
-    col_loop<N, KIND, true>(W, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv);
+    col_loop<N, KIND, true>(W, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv, sd.act_list);
   else
-    col_loop<N, KIND, false>(W, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv);
+    col_loop<N, KIND, false>(W, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv, sd.act_list);
 }
 
 
@@ -832,6 +855,14 @@ __device__ __forceinline__ void global_lines(const Geo& g, const SlotDesc& sd, L
   }
 }
 
+// any of the segment-lines this thread set up (global_lines) belongs to an iterated subdomain
+template <int L>
+__device__ __forceinline__ int own_lines_on(const LineInfo* info, int tid) {
+  int any = 0;
+  for (int l = tid; l < L; l += kThreads) any |= info[l].valid & info[l].on;
+  return any;
+}
+
 // z-axis neighbour slot of segment slot l (dir = -1 low, +1 high); -1 if absent
 __device__ __forceinline__ int z_neighbour(int l, int dir, const Geo& g) {
   const int P2 = g.P[2];
@@ -876,8 +907,10 @@ __device__ __forceinline__ void load_line_tables(float2* s_tw, float* s_C, const
 }
 
 // this thread's elements i + m N/R (butterfly q, line l) of a subdomain-major array, all loads
-// issued before any is used; lanes of an absent line read line 0 (in bounds, never used)
-template <class Tile, int N, int R, int PER, class Ptr>
+// issued before any is used (no branches, so the waits stay precise); lanes of an absent line,
+// and with ON_ONLY of a line whose subdomain is not iterated, read line 0 instead (in bounds,
+// cached, never used)
+template <class Tile, int N, int R, int PER, bool ON_ONLY, class Ptr>
 __device__ __forceinline__ void load_lines(float2 (&v)[PER][R], Ptr a, const LineInfo* info, int tid) {
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -885,14 +918,15 @@ __device__ __forceinline__ void load_lines(float2 (&v)[PER][R], Ptr a, const Lin
     const bool ok = bvalid<Tile, R>(q, tid);
     if (ok) Tile::template bf<R>(tid + q * Tile::NT, i, l);
     const LineInfo& li = info[l];
-    const int64_t base = (ok && li.valid) ? li.gbase + i : i;
+    const int64_t base = (ok && li.valid && (!ON_ONLY || li.on)) ? li.gbase + i : i;
 #pragma unroll
     for (int m = 0; m < R; ++m) v[q][m] = a[base + m * (N / R)];
   }
 }
 
-// z edge values of this thread's elements to LDS (first t to zlo, last t to zhi)
-template <class Tile, int N, int R, int PER, int TM>
+// z edge values of this thread's elements to LDS (first t to zlo, last t to zhi); with ON_ONLY
+// a line whose subdomain is not iterated has the edge values of its field, zero
+template <class Tile, int N, int R, int PER, int TM, bool ON_ONLY>
 __device__ __forceinline__ void put_z_edges(const float2 (&v)[PER][R], float2 (*zlo)[TM],
                                             float2 (*zhi)[TM], const LineInfo* info, int t, int tid) {
 #pragma unroll
@@ -901,11 +935,13 @@ __device__ __forceinline__ void put_z_edges(const float2 (&v)[PER][R], float2 (*
     int i, l;
     Tile::template bf<R>(tid + q * Tile::NT, i, l);
     if (!info[l].valid) continue;
+    const bool zero = ON_ONLY && !info[l].on;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int j = i + m * (N / R);
-      if (j < t) zlo[l][j] = v[q][m];
-      if (j >= N - t) zhi[l][j - (N - t)] = v[q][m];
+      const float2 e = zero ? make_float2(0.f, 0.f) : v[q][m];
+      if (j < t) zlo[l][j] = e;
+      if (j >= N - t) zhi[l][j - (N - t)] = e;
     }
   }
 }
@@ -936,7 +972,8 @@ __global__ __launch_bounds__(kThreads) void k_wpass(const SlotDesc* __restrict__
   const int tid = threadIdx.x;
   global_lines<L, SLAB_ONLY>(g, sd, info, tid);
   load_line_tables<N>(s_tw, s_C, tb, g, tid);
-  __syncthreads();
+  // W is written only on lines of iterated subdomains; a workgroup with none has nothing to do
+  if (!__syncthreads_or(own_lines_on<L>(info, tid))) return;
   const int t = g.t;
   const bool zc = g.a[2] > 0;
   const float cim = sd.c_im;
@@ -944,11 +981,13 @@ __global__ __launch_bounds__(kThreads) void k_wpass(const SlotDesc* __restrict__
   const auto E1 = gp(sd.slab[1][2]);
   const auto Y = gp(sd.ybox);
   const auto W = gp(sd.W);
+  // the edge-slab pass reads only iterated lines; the pass over every line (start of a solve,
+  // or lines of newly activated subdomains) reads all of them: x is zero where not iterated
   float2 xv[PER0][R0], bv[PER0][R0];
-  load_lines<Tile, N, R0, PER0>(xv, gp(sd.x), info, tid);
-  load_lines<Tile, N, R0, PER0>(bv, gp(sd.B), info, tid);
+  load_lines<Tile, N, R0, PER0, SLAB_ONLY>(xv, gp(sd.x), info, tid);
+  load_lines<Tile, N, R0, PER0, SLAB_ONLY>(bv, gp(sd.B), info, tid);
   if (zc) {
-    put_z_edges<Tile, N, R0, PER0, TM>(xv, zlo, zhi, info, t, tid);
+    put_z_edges<Tile, N, R0, PER0, TM, SLAB_ONLY>(xv, zlo, zhi, info, t, tid);
     __syncthreads();
     z_edge_terms<L, TM>(zlo, zhi, ez, info, g, s_C, cim, tid);
     __syncthreads();
@@ -964,7 +1003,7 @@ __global__ __launch_bounds__(kThreads) void k_wpass(const SlotDesc* __restrict__
     for (int m = 0; m < R0; ++m) {
       const int j = i + m * (N / R0);
       float2 w = make_float2(0.f, 0.f);
-      if (ok && li.valid) {
+      if (ok && li.valid && li.on) {
         float2 e = make_float2(0.f, 0.f);
         if (j >= li.jlo && j < li.jhi) e = Y[li.ybase + j];
         if (li.e0 >= 0) e = cadd(e, E0[li.e0 + j]);
@@ -982,7 +1021,7 @@ __global__ __launch_bounds__(kThreads) void k_wpass(const SlotDesc* __restrict__
     if (!bvalid<Tile, RL>(q, tid)) continue;
     int i, l;
     Tile::template bf<RL>(tid + q * Tile::NT, i, l);
-    if (!info[l].valid) continue;
+    if (!info[l].valid || !info[l].on) continue;
 #pragma unroll
     for (int m = 0; m < RL; ++m) W[info[l].gbase + i + m * (N / RL)] = o[q][m];
   }
@@ -1011,7 +1050,11 @@ __global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__
   global_lines<L, false>(g, sd, info, tid);
   load_line_tables<N>(s_tw, s_C, tb, g, tid);
   if (tid == 0) any_plain = 0;
-  __syncthreads();
+  if (!__syncthreads_or(own_lines_on<L>(info, tid))) {
+    // every line here belongs to a subdomain that is not iterated (activation)
+    if (tid == 0) gp(sd.part_main)[blockIdx.x] = 0.0;
+    return;
+  }
   const int t = g.t;
   const bool zc = g.a[2] > 0;
   const float cim = sd.c_im, alpha = sd.alpha;
@@ -1019,9 +1062,9 @@ __global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__
   const auto W = gp(sd.W);
   // every global read of the tile is issued here: v of iteration n, x_n and B
   float2 vin[PI][RI], xv[PER0][R0], bv[PER0][R0];
-  load_lines<Tile, N, RI, PI>(vin, W, info, tid);
-  load_lines<Tile, N, R0, PER0>(xv, X, info, tid);
-  load_lines<Tile, N, R0, PER0>(bv, gp(sd.B), info, tid);
+  load_lines<Tile, N, RI, PI, true>(vin, W, info, tid);
+  load_lines<Tile, N, R0, PER0, true>(xv, X, info, tid);
+  load_lines<Tile, N, R0, PER0, true>(bv, gp(sd.B), info, tid);
   float2 u[PER0][R0];
   fft_tile<Tile, N, true, +1>(vin, u, lds, s_tw, tid);
   // u = x - v; the z edge terms of u
@@ -1030,7 +1073,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__
 #pragma unroll
     for (int m = 0; m < R0; ++m) u[q][m] = csub(xv[q][m], u[q][m]);
   if (zc) {
-    put_z_edges<Tile, N, R0, PER0, TM>(u, zlo, zhi, info, t, tid);
+    put_z_edges<Tile, N, R0, PER0, TM, true>(u, zlo, zhi, info, t, tid);
     __syncthreads();
     z_edge_terms<L, TM>(zlo, zhi, ez, info, g, s_C, cim, tid);
     __syncthreads();
@@ -1045,7 +1088,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__
     const bool ok = bvalid<Tile, R0>(q, tid);
     if (ok) Tile::template bf<R0>(tid + q * Tile::NT, i, l);
     const LineInfo& li = info[l];
-    if (!(ok && li.valid)) continue;
+    if (!(ok && li.valid && li.on)) continue;
     const bool slab = li.e0 >= 0 || li.e1 >= 0;
 #pragma unroll
     for (int m = 0; m < R0; ++m) {
@@ -1073,7 +1116,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__
   if (any_plain) {
     const auto Y = gp(sd.ybox);
     if (zc) {
-      put_z_edges<Tile, N, R0, PER0, TM>(xv, zlo, zhi, info, t, tid);
+      put_z_edges<Tile, N, R0, PER0, TM, true>(xv, zlo, zhi, info, t, tid);
       __syncthreads();
       z_edge_terms<L, TM>(zlo, zhi, ez, info, g, s_C, cim, tid);
       __syncthreads();
@@ -1085,7 +1128,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__
       const bool ok = bvalid<Tile, R0>(q, tid);
       if (ok) Tile::template bf<R0>(tid + q * Tile::NT, i, l);
       const LineInfo& li = info[l];
-      const bool plain = ok && li.valid && li.e0 < 0 && li.e1 < 0;
+      const bool plain = ok && li.valid && li.on && li.e0 < 0 && li.e1 < 0;
 #pragma unroll
       for (int m = 0; m < R0; ++m) {
         const int j = i + m * (N / R0);
@@ -1107,7 +1150,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__
       int i, l;
       Tile::template bf<RL>(tid + q * Tile::NT, i, l);
       const LineInfo& li = info[l];
-      if (!li.valid || li.e0 >= 0 || li.e1 >= 0) continue;
+      if (!li.valid || !li.on || li.e0 >= 0 || li.e1 >= 0) continue;
 #pragma unroll
       for (int m = 0; m < RL; ++m) W[li.gbase + i + m * (N / RL)] = o[q][m];
     }
@@ -1127,8 +1170,8 @@ __global__ __launch_bounds__(kThreads) void k_slabA(const SlotDesc* __restrict__
   const int64_t per_sub = (int64_t)per_col * n2;
   const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   double acc = 0.0;
-  if (gid < (int64_t)g.S * per_sub) {
-    const int s = (int)(gid / per_sub);
+  const int s = (int)(gid / (per_sub > 0 ? per_sub : 1));
+  if (gid < (int64_t)g.S * per_sub && sub_on(sd.act, s)) {
     const int64_t r = gid - (int64_t)s * per_sub;
     const int k = (int)(r / n2);
     const int j = (int)(r - (int64_t)k * n2);
@@ -1157,6 +1200,86 @@ __global__ __launch_bounds__(kThreads) void k_slabA(const SlotDesc* __restrict__
   }
   const double ssum = block_sum(acc, red);
   if (threadIdx.x == 0) gp(sd.part_face)[blockIdx.x] = ssum;
+}
+
+// ---------------------------------------------------------------------------
+// Subdomain activation (Sec. 3.1, end): the field an iterated neighbour transfers into a
+// subdomain that is not iterated.  There x = 0, so its edge terms are exactly the transfer:
+// along x and y they are the corrections of the iterate the slab pass already wrote
+// (E = -c C h of the neighbour), along z they are formed here from the neighbours' t edge
+// values.  Workgroup b of subdomain s writes the partial sum of |E|^2 over its share of the
+// faces to xfer[s * kXferBlocks + b] (zero for iterated subdomains).
+// ---------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(kThreads) void k_xfer(const SlotDesc* __restrict__ tab, Geo g,
+                                                   const float* __restrict__ C) {
+  const SlotDesc& sd = tab[blockIdx.y];
+  if (sd.xfer == nullptr || sd.st->done == kIdle) return;
+  __shared__ double red[kThreads / 64];
+  const int s = blockIdx.x / kXferBlocks, b = blockIdx.x - s * kXferBlocks;
+  const int64_t step = (int64_t)kXferBlocks * kThreads;
+  double acc = 0.0;
+  if (!sub_on(sd.act, s)) {
+    for (int d = 0; d < 2; ++d) {
+      if (!g.a[d]) continue;
+      const int64_t plane = d == 0 ? (int64_t)g.n[1] * g.n[2] : (int64_t)g.n[0] * g.n[2];
+      const int64_t cnt = 2 * (int64_t)T * plane;  // both sides of subdomain s
+      const auto E = gp(sd.slab[d][2]) + (int64_t)s * cnt;
+      for (int64_t e = (int64_t)b * kThreads + threadIdx.x; e < cnt; e += step) {
+        const float2 v = E[e];
+        acc += (double)v.x * v.x + (double)v.y * v.y;
+      }
+    }
+    const int P2 = g.P[2];
+    if (g.a[2] == 2) {
+      const int s2 = s % P2;
+      int slo = s2 - 1, shi = s2 + 1;
+      if (slo < 0) slo = g.periodic[2] ? P2 - 1 : -1;
+      if (shi >= P2) shi = g.periodic[2] ? 0 : -1;
+      if (slo >= 0) slo = s - s2 + slo;
+      if (shi >= 0) shi = s - s2 + shi;
+      const bool lo_on = slo >= 0 && sub_on(sd.act, slo);
+      const bool hi_on = shi >= 0 && sub_on(sd.act, shi);
+      const int n2 = g.n[2];
+      const int64_t nl = (int64_t)g.n[0] * g.n[1];
+      const double c2 = (double)sd.c_im * (double)sd.c_im;
+      const auto X = gp(sd.x);
+      for (int64_t k = (int64_t)b * kThreads + threadIdx.x; k < nl; k += step) {
+        if (lo_on) {  // last T values of the lower neighbour enter through the low edge
+          float2 h[T];
+#pragma unroll
+          for (int j = 0; j < T; ++j) h[j] = X[((int64_t)slo * nl + k) * n2 + (n2 - T) + j];
+#pragma unroll
+          for (int a = 0; a < T; ++a) {
+            float2 e = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+              e.x = fmaf(C[a * T + j], h[j].x, e.x);
+              e.y = fmaf(C[a * T + j], h[j].y, e.y);
+            }
+            acc += c2 * ((double)e.x * e.x + (double)e.y * e.y);
+          }
+        }
+        if (hi_on) {  // first T values of the upper neighbour enter through the high edge
+          float2 l[T];
+#pragma unroll
+          for (int j = 0; j < T; ++j) l[j] = X[((int64_t)shi * nl + k) * n2 + j];
+#pragma unroll
+          for (int a = 0; a < T; ++a) {
+            float2 e = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+              e.x = fmaf(C[j * T + a], l[j].x, e.x);
+              e.y = fmaf(C[j * T + a], l[j].y, e.y);
+            }
+            acc += c2 * ((double)e.x * e.x + (double)e.y * e.y);
+          }
+        }
+      }
+    }
+  }
+  const double sum = block_sum(acc, red);
+  if (threadIdx.x == 0) sd.xfer[blockIdx.x] = sum;
 }
 
 // ---------------------------------------------------------------------------
@@ -1830,6 +1953,20 @@ hipError_t launch_reduce(const SlotDesc* tab, int nslots, const Geo& g, int64_t 
   (void)g;
   hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks, nslots), dim3(kThreads), 0, s, tab, n_main, n_face);
   hipLaunchKernelGGL(k_reduce2, dim3(nslots), dim3(64), 0, s, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_xfer(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, hipStream_t s) {
+  dim3 grid((unsigned)(g.S * kXferBlocks), nslots);
+  switch (g.t) {
+#define MBS_T(TT) \
+  case TT: hipLaunchKernelGGL(k_xfer<TT>, grid, dim3(kThreads), 0, s, tab, g, tb.C); break;
+    MBS_T(1) MBS_T(2) MBS_T(3) MBS_T(4) MBS_T(5) MBS_T(6) MBS_T(7) MBS_T(8)
+    MBS_T(9) MBS_T(10) MBS_T(11) MBS_T(12) MBS_T(13) MBS_T(14) MBS_T(15) MBS_T(16)
+#undef MBS_T
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

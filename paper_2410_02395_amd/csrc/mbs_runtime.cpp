@@ -100,6 +100,15 @@ struct Slot {
   int64_t launched = 0;    // iterations enqueued since the solve started
   int32_t max_iter = 0;
   mbs_result res{};
+  // subdomain activation (Sec. 3.1): bit mask and ascending list of iterated subdomains
+  uint32_t* act_d = nullptr;      // device, act_words entries
+  int32_t* list_d = nullptr;      // device, S entries
+  uint32_t* fresh_d = nullptr;    // device, subdomains activated at the last chunk boundary
+  uint32_t* stage = nullptr;      // pinned staging: act words, fresh words, list
+  std::vector<uint32_t> act_h;    // host copy of the mask
+  int32_t n_act = 0;
+  int64_t sub_iters = 0;          // sum over iterations of the subdomains iterated
+  int32_t iter_seen = 0;          // iterations accounted in sub_iters
 };
 
 }  // namespace
@@ -119,6 +128,11 @@ struct mbs_plan_s {
   bool use_graph = true;
   bool timing = false;
   int64_t n_main = 0, n_face = 0;
+  double activation = 0;    // > 0: subdomain activation with this threshold (relative to rho_ref)
+  int act_words = 0;
+  double* d_xfer = nullptr;       // nslots x S x kXferBlocks transfer partials
+  double* h_xfer = nullptr;       // pinned, 2 x the above
+  SlotDesc* d_fresh_tab = nullptr;  // per slot: descriptor that writes W only on fresh subdomains
   // tables
   float2* tw[3] = {};
   float* p2[3] = {};
@@ -170,6 +184,7 @@ mbs_status validate(const mbs_plan_desc* d, Geo* g) {
   if (d->max_batch < 1 || d->max_batch > 4096) return MBS_EINVAL;
   if (!(d->alpha > 0.0 && d->alpha <= 1.0)) return MBS_EINVAL;
   if (d->check_every < 0) return MBS_EINVAL;
+  if (!(d->activation >= 0.0 && std::isfinite(d->activation))) return MBS_EINVAL;
   Geo geo{};
   int64_t sub = 1, vox = 1;
   int S = 1;
@@ -217,6 +232,11 @@ mbs_status validate(const mbs_plan_desc* d, Geo* g) {
       geo.reg_count[r] = (int64_t)geo.reg_ext[r][0] * geo.reg_ext[r][1] * geo.reg_ext[r][2];
       geo.face_vox += geo.reg_count[r];
     }
+  }
+  if (d->activation > 0.0) {
+    // activation skips whole subdomains of the fused z-pass sequence
+    if (S > kMaxActSub) return MBS_EUNSUPPORTED;
+    if ((d->flags & MBS_NO_FUSION) || !fusion_supported(geo)) return MBS_EUNSUPPORTED;
   }
   *g = geo;
   return MBS_OK;
@@ -278,7 +298,12 @@ void fill_desc(mbs_plan p, int i) {
   d.part_face = s.part_face;
   d.hist = s.hist;
   d.part_red = s.part_red;
-  d.active = 1;
+  const bool act = p->activation > 0.0 && s.act_d != nullptr;
+  d.act = act ? s.act_d : nullptr;
+  d.act_list = act ? s.list_d : nullptr;
+  d.n_act = act ? s.n_act : p->geo.S;
+  d.xfer = act ? p->d_xfer + (size_t)i * p->geo.S * kXferBlocks : nullptr;
+  d.pad = 0;
 }
 
 mbs_status push_desc(mbs_plan p, int i) {
@@ -404,6 +429,7 @@ mbs_status build_graph(mbs_plan p) {
   hipError_t e = hipSuccess;
   for (int it = 0; it < p->check_every && e == hipSuccess; ++it)
     e = enqueue_iteration(p, p->d_tab, p->nslots, p->cap_stream);
+  if (e == hipSuccess && p->activation > 0.0) e = launch_xfer(p->d_tab, p->nslots, p->geo, p->tb, p->cap_stream);
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -435,12 +461,18 @@ mbs_status launch_chunk(mbs_plan p) {
     p->tcount = 0;
     for (int64_t it = 0; it < n_it; ++it)
       HIP_TRY(enqueue_iteration(p, p->d_tab, p->nslots, p->stream));
+    if (p->activation > 0.0) HIP_TRY(launch_xfer(p->d_tab, p->nslots, p->geo, p->tb, p->stream));
   }
   for (auto& s : p->slots)
     if (s.busy && !s.finishing) s.launched += n_it;
   p->cur_buf ^= 1;
   SlotState* hb = p->h_states + p->cur_buf * (p->nslots + 1);
   HIP_TRY(hipMemcpyAsync(hb, p->d_states, sizeof(SlotState) * p->nslots, hipMemcpyDeviceToHost, p->stream));
+  if (p->activation > 0.0) {
+    const size_t nx = (size_t)p->nslots * p->geo.S * kXferBlocks;
+    HIP_TRY(hipMemcpyAsync(p->h_xfer + p->cur_buf * nx, p->d_xfer, nx * sizeof(double), hipMemcpyDeviceToHost,
+                           p->stream));
+  }
   HIP_TRY(hipEventRecord(p->chunk_ev, p->stream));
   p->in_flight = true;
   p->chunk_seq++;
@@ -485,12 +517,105 @@ mbs_status retire_finished(mbs_plan p, const SlotState* hs) {
     r.normC = p->normC;
     r.rho_ref = st.rho_ref;
     r.status = status_of(st.done);
+    r.subdomain_iterations = s.sub_iters;
     s.rho_ref = st.rho_ref;
     s.last_status = r.status;
     if (s.field_out) HIP_TRY(launch_gather(s.x, p->geo, (float2*)s.field_out, p->stream));
     HIP_TRY(hipEventRecord(s.done_ev, p->stream));
     s.finishing = true;
   }
+  return MBS_OK;
+}
+
+// copy a slot's activation mask, its list of iterated subdomains and (optionally) the mask of
+// newly activated subdomains to the device, through the slot's pinned staging buffer
+mbs_status upload_activation(mbs_plan p, int i, const std::vector<uint32_t>* fresh) {
+  Slot& s = p->slots[i];
+  const int S = p->geo.S, W = p->act_words;
+  uint32_t* stg = s.stage;  // [W mask][W fresh][S list]
+  int32_t* list = reinterpret_cast<int32_t*>(stg + 2 * W);
+  std::copy(s.act_h.begin(), s.act_h.end(), stg);
+  int n = 0;
+  for (int sub = 0; sub < S; ++sub)
+    if ((s.act_h[sub >> 5] >> (sub & 31)) & 1u) list[n++] = sub;
+  s.n_act = n;
+  HIP_TRY(hipMemcpyAsync(s.act_d, stg, W * sizeof(uint32_t), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(s.list_d, list, S * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+  if (fresh) {
+    std::copy(fresh->begin(), fresh->end(), stg + W);
+    HIP_TRY(hipMemcpyAsync(s.fresh_d, stg + W, W * sizeof(uint32_t), hipMemcpyHostToDevice, p->stream));
+  }
+  return MBS_OK;
+}
+
+// Subdomain activation (Sec. 3.1, end), at a chunk boundary: a subdomain that is not iterated
+// joins when the field its iterated neighbours transfer into it (2-norm of the edge terms, from
+// k_xfer at the end of the chunk) exceeds activation * rho_ref.  Its w is formed at once (x is
+// still zero there), the divergence test is reset for one iteration (the residual grows by the
+// new subdomain's share), and a slot that had converged on the old set iterates on.
+mbs_status apply_activation(mbs_plan p, SlotState* hs, const double* hx) {
+  const int S = p->geo.S, W = p->act_words;
+  for (int i = 0; i < p->nslots; ++i) {
+    Slot& s = p->slots[i];
+    if (!s.busy || s.finishing || p->chunk_seq <= s.start_seq) continue;
+    SlotState& st = hs[i];
+    if (st.done != kRunning && st.done != kConverged) continue;
+    if (!(st.rho_ref > 0.0)) continue;
+    const double thr = p->activation * st.rho_ref;
+    std::vector<uint32_t> fresh(W, 0u);
+    bool any = false;
+    for (int sub = 0; sub < S; ++sub) {
+      if ((s.act_h[sub >> 5] >> (sub & 31)) & 1u) continue;
+      const double* part = hx + ((size_t)i * S + sub) * kXferBlocks;
+      double sum = 0.0;
+      for (int b = 0; b < kXferBlocks; ++b) sum += part[b];
+      if (sum > thr * thr) {
+        fresh[sub >> 5] |= 1u << (sub & 31);
+        any = true;
+      }
+    }
+    if (!any) continue;
+    for (int w = 0; w < W; ++w) s.act_h[w] |= fresh[w];
+    mbs_status r = upload_activation(p, i, &fresh);
+    if (r != MBS_OK) return r;
+    r = push_desc(p, i);
+    if (r != MBS_OK) return r;
+    SlotDesc fd = p->h_tab[i];
+    fd.act = s.fresh_d;  // write W on the fresh subdomains only
+    fd.act_list = nullptr;
+    fd.xfer = nullptr;
+    HIP_TRY(put_desc(p->d_fresh_tab + i, fd, p->stream));
+    SlotState ns = st;
+    ns.done = kRunning;
+    ns.eps_prev = HUGE_VAL;
+    HIP_TRY(put_state(p->d_states + i, ns, p->stream));
+    HIP_TRY(launch_wpass(p->d_fresh_tab + i, 1, p->geo, p->tb, 0, p->stream));
+    st.done = kRunning;  // not finished after all
+  }
+  return MBS_OK;
+}
+
+// initial set of iterated subdomains: those holding source (all of them with a given start
+// field or without a source)
+mbs_status init_activation(mbs_plan p, int i, bool all) {
+  Slot& s = p->slots[i];
+  const Geo& g = p->geo;
+  s.act_h.assign(p->act_words, 0u);
+  for (int sub = 0; sub < g.S; ++sub) {
+    const int sc[3] = {sub / (g.P[1] * g.P[2]), (sub / g.P[2]) % g.P[1], sub % g.P[2]};
+    bool on = true;
+    if (!all)
+      for (int k = 0; k < 3; ++k) {
+        const int lo = sc[k] * g.n[k], hi = lo + g.n[k];
+        if (s.ylo[k] >= hi || s.ylo[k] + s.yext[k] <= lo) on = false;
+      }
+    if (on) s.act_h[sub >> 5] |= 1u << (sub & 31);
+  }
+  mbs_status r = upload_activation(p, i, nullptr);
+  if (r != MBS_OK) return r;
+  // u of subdomains that are not iterated is zero; their edge values must read as zero
+  for (int d = 0; d < 2; ++d)
+    if (g.a[d]) HIP_TRY(launch_zero(s.slab[d][1], slab_elems(g, d), p->stream));
   return MBS_OK;
 }
 
@@ -512,7 +637,21 @@ mbs_status progress(mbs_plan p, bool block) {
     }
     p->in_flight = false;
     collect_timing(p);
-    mbs_status st = retire_finished(p, p->h_states + p->cur_buf * (p->nslots + 1));
+    SlotState* hs = p->h_states + p->cur_buf * (p->nslots + 1);
+    mbs_status st = MBS_OK;
+    for (int i = 0; i < p->nslots; ++i) {  // subdomain-iterations of the chunk, on the set it ran with
+      Slot& s = p->slots[i];
+      if (!s.busy || s.finishing || p->chunk_seq <= s.start_seq) continue;
+      const int32_t n_set = p->activation > 0.0 ? s.n_act : p->geo.S;
+      s.sub_iters += (int64_t)(hs[i].iter - s.iter_seen) * n_set;
+      s.iter_seen = hs[i].iter;
+    }
+    if (p->activation > 0.0) {
+      const size_t nx = (size_t)p->nslots * p->geo.S * kXferBlocks;
+      st = apply_activation(p, hs, p->h_xfer + p->cur_buf * nx);
+      if (st != MBS_OK) return st;
+    }
+    st = retire_finished(p, hs);
     if (st != MBS_OK) return st;
   }
   if (any_running(p)) return launch_chunk(p);
@@ -568,6 +707,10 @@ mbs_status probe_norm(mbs_plan p, int slot, float2* xsrc, double* rho) {
   d.x = xsrc;
   d.alpha = 0.f;
   d.st = p->d_states + p->nslots;
+  d.act = nullptr;  // a residual evaluation covers every subdomain
+  d.act_list = nullptr;
+  d.n_act = p->geo.S;
+  d.xfer = nullptr;
   SlotState st{};
   st.done = kRunning;
   st.probe = 1;
@@ -608,6 +751,10 @@ mbs_status start_solve(mbs_plan p, int slot, const void* src, double tol, int32_
   if (x0 && !field) return MBS_EINVAL;
   mbs_status st = prepare_source(p, slot, src);
   if (st != MBS_OK) return st;
+  if (p->activation > 0.0) {
+    st = init_activation(p, slot, x0 || !s.has_source);
+    if (st != MBS_OK) return st;
+  }
   if (x0) HIP_TRY(launch_scatter((const float2*)field, p->geo, s.x, p->stream));
   else HIP_TRY(launch_zero(s.x, p->geo.vox, p->stream));
   st = push_desc(p, slot);
@@ -637,6 +784,8 @@ mbs_status start_solve(mbs_plan p, int slot, const void* src, double tol, int32_
     HIP_TRY(launch_wpass(one, 1, p->geo, p->tb, 0, p->stream));
   }
   s.busy = true;
+  s.sub_iters = 0;
+  s.iter_seen = 0;
   s.start_seq = p->chunk_seq;
   s.finishing = false;
   s.field_out = field;
@@ -694,6 +843,9 @@ mbs_status mbs_plan_bytes(const mbs_plan_desc* desc, size_t* device_bytes) {
   for (int d = 0; d < 3; ++d) b += (size_t)g.n[d] * (sizeof(float2) + sizeof(float));
   b += (size_t)kMaxT * kMaxT * sizeof(float);
   b += (size_t)setup_blocks(g) * (sizeof(MediumStats) + sizeof(double)) + 64;
+  if (desc->activation > 0.0)  // masks, lists, transfer partials, fresh descriptors
+    b += (size_t)desc->max_batch * ((2 * (size_t)((g.S + 31) / 32) + g.S) * sizeof(uint32_t) +
+                                    (size_t)g.S * kXferBlocks * sizeof(double) + sizeof(SlotDesc));
   *device_bytes = b;
   return MBS_OK;
 }
@@ -710,6 +862,9 @@ mbs_status mbs_plan_destroy(mbs_plan p) {
   for (void* a : p->allocs)
     if (a) (void)hipFree(a);
   if (p->h_states) (void)hipHostFree(p->h_states);
+  if (p->h_xfer) (void)hipHostFree(p->h_xfer);
+  for (auto& s : p->slots)
+    if (s.stage) (void)hipHostFree(s.stage);
   if (p->h_bbox) (void)hipHostFree(p->h_bbox);
   delete p;
   return MBS_OK;
@@ -730,6 +885,7 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
   p->corr = g.a[0] || g.a[1] || g.a[2];
   p->corr01 = g.a[0] || g.a[1];
   p->fused = !(desc->flags & MBS_NO_FUSION) && fusion_supported(g);
+  p->activation = desc->activation;
   p->check_every = desc->check_every > 0 ? desc->check_every : 16;
   p->timing = (desc->flags & MBS_TIMING) != 0;
   p->use_graph = !(desc->flags & (MBS_NO_GRAPH | MBS_TIMING));
@@ -800,6 +956,24 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
     if ((st = dalloc(p, &s.hist, kHistCap)) != MBS_OK) return fail(st);
     if ((st = dalloc(p, &s.part_red, kReduceBlocks)) != MBS_OK) return fail(st);
     if (hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming) != hipSuccess) return fail(MBS_EHIP);
+  }
+  if (p->activation > 0.0) {
+    const int S = g.S, W = (S + 31) / 32;
+    p->act_words = W;
+    for (int i = 0; i < p->nslots; ++i) {
+      Slot& s = p->slots[i];
+      if ((st = dalloc(p, &s.act_d, W)) != MBS_OK) return fail(st);
+      if ((st = dalloc(p, &s.fresh_d, W)) != MBS_OK) return fail(st);
+      if ((st = dalloc(p, &s.list_d, S)) != MBS_OK) return fail(st);
+      if (hipHostMalloc((void**)&s.stage, (2 * (size_t)W + S) * sizeof(uint32_t), 0) != hipSuccess)
+        return fail(MBS_ENOMEM);
+      s.act_h.assign(W, ~0u);
+      s.n_act = S;
+    }
+    const size_t nx = (size_t)p->nslots * S * kXferBlocks;
+    if ((st = dalloc(p, &p->d_xfer, nx)) != MBS_OK) return fail(st);
+    if (hipHostMalloc((void**)&p->h_xfer, 2 * nx * sizeof(double), 0) != hipSuccess) return fail(MBS_ENOMEM);
+    if ((st = dalloc(p, &p->d_fresh_tab, p->nslots)) != MBS_OK) return fail(st);
   }
   if ((st = dalloc(p, &p->d_tab, p->nslots)) != MBS_OK) return fail(st);
   if ((st = dalloc(p, &p->d_probe_tab, 1)) != MBS_OK) return fail(st);

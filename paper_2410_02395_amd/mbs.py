@@ -57,6 +57,7 @@ class PlanDesc(ctypes.Structure):
         ("alpha", ctypes.c_double),
         ("flags", ctypes.c_uint32),
         ("check_every", ctypes.c_int32),
+        ("activation", ctypes.c_double),
     ]
 
 
@@ -75,6 +76,7 @@ class Result(ctypes.Structure):
         ("normC", ctypes.c_double),
         ("rho_ref", ctypes.c_double),
         ("status", ctypes.c_int32),
+        ("subdomain_iterations", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -129,7 +131,7 @@ def _check(status: int, what: str):
 
 
 def make_desc(shape, split=(1, 1, 1), periodic=(1, 1, 1), t=8, max_batch=1, alpha=0.75,
-              flags=0, check_every=0) -> PlanDesc:
+              flags=0, check_every=0, activation=0.0) -> PlanDesc:
     d = PlanDesc()
     for k in range(3):
         d.shape[k] = int(shape[k])
@@ -140,15 +142,16 @@ def make_desc(shape, split=(1, 1, 1), periodic=(1, 1, 1), t=8, max_batch=1, alph
     d.alpha = float(alpha)
     d.flags = int(flags)
     d.check_every = int(check_every)
+    d.activation = float(activation)
     return d
 
 
 def plan_bytes(shape, split=(1, 1, 1), periodic=(1, 1, 1), t=8, max_batch=1, alpha=0.75,
-               flags=0, check_every=0) -> int:
+               flags=0, check_every=0, activation=0.0) -> int:
     lib = load_library()
     out = ctypes.c_size_t(0)
     _check(lib.mbs_plan_bytes(ctypes.byref(make_desc(shape, split, periodic, t, max_batch, alpha,
-                                                     flags, check_every)), ctypes.byref(out)),
+                                                     flags, check_every, activation)), ctypes.byref(out)),
            "mbs_plan_bytes")
     return int(out.value)
 
@@ -165,7 +168,7 @@ class Plan:
     """One solver plan (grid, decomposition, slots) on the current device."""
 
     def __init__(self, shape, split=(1, 1, 1), periodic=(1, 1, 1), t=8, max_batch=1, alpha=0.75,
-                 flags=0, check_every=0, stream: Optional[torch.cuda.Stream] = None):
+                 flags=0, check_every=0, stream: Optional[torch.cuda.Stream] = None, activation=0.0):
         self._lib = load_library()
         self.shape = tuple(int(s) for s in shape)
         self.split = tuple(int(s) for s in split)
@@ -175,7 +178,8 @@ class Plan:
         self.alpha = float(alpha)
         self.flags = int(flags)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self._desc = make_desc(shape, split, periodic, t, max_batch, alpha, flags, check_every)
+        self.activation = float(activation)
+        self._desc = make_desc(shape, split, periodic, t, max_batch, alpha, flags, check_every, activation)
         h = ctypes.c_void_p(0)
         _check(self._lib.mbs_plan_create(ctypes.byref(self._desc), ctypes.c_void_p(self.stream.cuda_stream),
                                          ctypes.byref(h)), "mbs_plan_create")

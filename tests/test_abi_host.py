@@ -83,7 +83,7 @@ def test_struct_layouts_match_header(mbs_mod, tmp_path):
 
 
 def _desc(mbs, shape=(64, 64, 64), split=(1, 1, 1), periodic=(1, 1, 1), t=8, max_batch=1, alpha=0.75,
-          check_every=0):
+          check_every=0, flags=0, activation=0.0):
     d = mbs.PlanDesc()
     d.shape[:] = shape
     d.split[:] = split
@@ -91,8 +91,9 @@ def _desc(mbs, shape=(64, 64, 64), split=(1, 1, 1), periodic=(1, 1, 1), t=8, max
     d.t = t
     d.max_batch = max_batch
     d.alpha = alpha
-    d.flags = 0
+    d.flags = flags
     d.check_every = check_every
+    d.activation = activation
     return d
 
 
@@ -135,10 +136,26 @@ def test_plan_bytes_memory_model(mbs_mod, lib):
     (dict(max_batch=0), "MBS_EINVAL"),
     (dict(check_every=-1), "MBS_EINVAL"),
     (dict(shape=(4096, 1024, 1024), split=(4, 1, 1)), "MBS_EUNSUPPORTED"),  # above 2^31 voxels
+    (dict(activation=-1e-3), "MBS_EINVAL"),
+    (dict(activation=float("nan")), "MBS_EINVAL"),
+    # activation needs the fused z pass and at most 4096 subdomains
+    (dict(shape=(64, 64, 64), split=(2, 2, 2), periodic=(0, 0, 0), flags=0x10, activation=1e-4),
+     "MBS_EUNSUPPORTED"),
+    (dict(shape=(512, 512, 16), split=(64, 64, 2), periodic=(0, 0, 0), t=4, activation=1e-4),
+     "MBS_EUNSUPPORTED"),
 ])
 def test_plan_bytes_rejects_what_plan_create_rejects(mbs_mod, lib, kw, status):
     st, _ = _bytes(mbs_mod, lib, **kw)
     assert st == getattr(mbs_mod, status)
+
+
+def test_plan_bytes_with_activation(mbs_mod, lib):
+    """Activation adds per-slot masks, lists and transfer partials: a few kB, not arrays."""
+    kw = dict(shape=(1024, 1024, 1024), split=(2, 2, 2), periodic=(0, 0, 0), max_batch=2)
+    st0, b0 = _bytes(mbs_mod, lib, **kw)
+    st1, b1 = _bytes(mbs_mod, lib, activation=1e-4, **kw)
+    assert st0 == st1 == mbs_mod.MBS_OK
+    assert 0 < b1 - b0 < 64 << 10
 
 
 def test_null_arguments_are_rejected_without_a_device(mbs_mod, lib):
