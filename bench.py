@@ -194,6 +194,54 @@ def serving_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def tolerance_study(args, w, n, S, mbs):
+    """Solve to a tolerance with every subdomain iterated and with subdomain activation
+    (Sec. 3.1) at each threshold: iterations, subdomain-iterations, wall time, the full
+    residual of each field (every subdomain) and its difference from the field of the run
+    that iterates every subdomain."""
+    import torch
+    dev = n.device
+    runs = {}
+    ref = None
+    taus = [0.0] + [float(x) for x in str(args.activation).split(",") if x]
+    for act in taus:
+        name = "all_subdomains" if act == 0.0 else f"activation_{act:g}"
+        plan = mbs.Plan(w.shape, w.split, w.periodic, w.t, 1, w.alpha, 0, 50, activation=act)
+        plan.set_medium(0, n, w.k_vac, w.ramp_width, w.ramp_max)
+        out = torch.empty(w.shape, dtype=torch.complex64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, res = plan.solve(0, S, args.tol, 100000, out=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        full = plan.residual(0, out)
+        plan.close()
+        runs[name] = {"iterations": res["iterations"], "subdomain_iterations": res["subdomain_iterations"],
+                      "seconds": round(dt, 3), "rel_residual": res["rel_residual"], "full_residual": full,
+                      "converged": res["converged"]}
+        if ref is None:
+            ref = out
+        else:
+            runs[name]["field_rel_difference"] = float(torch.linalg.vector_norm(out - ref)
+                                                       / torch.linalg.vector_norm(ref))
+            del out
+        print(f"[bench] {name}: {runs[name]}", file=sys.stderr, flush=True)
+    best = min((r["seconds"] for k, r in runs.items() if k != "all_subdomains"), default=None)
+    line = {
+        "metric": "MBS solve to tolerance: wall time with and without subdomain activation",
+        "value": runs["all_subdomains"]["seconds"] / best if best else None,
+        "unit": "speed-up",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "shape": list(w.shape), "split": list(w.split), "tol": args.tol,
+                   "activation": taus[1:]},
+        "runs": runs,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +256,12 @@ def main():
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--no-fusion", action="store_true",
                     help="separate last inverse and next forward z passes (for comparison)")
+    ap.add_argument("--tol", type=float, default=0.0,
+                    help="solve the workload to this relative residual, with and without subdomain "
+                         "activation, and report iterations and wall time instead of the fixed-count run")
+    ap.add_argument("--activation", default="1e-3",
+                    help="comma-separated activation thresholds (relative to ||Gamma^-1 y||) of the "
+                         "--tol study")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: every subdomain of the workload is resident on a single "
@@ -239,6 +293,9 @@ def main():
     for d in range(3):
         box *= int(nz[:, d].max() - nz[:, d].min() + 1)
     torch.cuda.synchronize()
+    if args.tol > 0:
+        tolerance_study(args, w, n, S, mbs)
+        return
     flags = mbs.MBS_TIMING | (mbs.MBS_NO_FUSION if args.no_fusion else 0)
     plan = mbs.Plan(w.shape, w.split, w.periodic, w.t, 1, w.alpha, flags=flags,
                     check_every=min(50, max(1, args.steps)))
