@@ -219,7 +219,16 @@ __host__ __device__ constexpr int col_waves_c(int n) { return col_threads_c(n) =
 #ifndef MBS_COL_PREFETCH
 #define MBS_COL_PREFETCH 1
 #endif
-// tile shape of the x pass (two FFTs per column) for 384 <= N <= 512
+// parts in which the next tile's loads are issued over an iteration of the persistent column
+// loop: x pass (two FFTs) and y passes (one FFT)
+#ifndef MBS_GREEN_SPLIT
+#define MBS_GREEN_SPLIT 3
+#endif
+#ifndef MBS_COL_SPLIT
+#define MBS_COL_SPLIT 1
+#endif
+// tile shape of the x pass (two FFTs per column) for MBS_GREEN_MIN_N <= N <= 512 (half the
+// threads below 384: eight elements per thread either way)
 #ifndef MBS_GREEN_WC
 #define MBS_GREEN_WC 16
 #endif
@@ -229,15 +238,21 @@ __host__ __device__ constexpr int col_waves_c(int n) { return col_threads_c(n) =
 #ifndef MBS_GREEN_WAVES
 #define MBS_GREEN_WAVES 4
 #endif
+#ifndef MBS_GREEN_MIN_N
+#define MBS_GREEN_MIN_N 256
+#endif
+__host__ __device__ constexpr bool green_tile_c(int n, int kind) {
+  return kind == 2 && n >= MBS_GREEN_MIN_N && n <= 512;
+}
 // per pass kind: columns per tile, threads per workgroup, minimum waves per SIMD
 __host__ __device__ constexpr int col_wc_c(int n, int kind) {
-  return (kind == 2 && n >= 384 && n <= 512) ? MBS_GREEN_WC : cols_per_tile_c(n);
+  return green_tile_c(n, kind) ? MBS_GREEN_WC : cols_per_tile_c(n);
 }
 __host__ __device__ constexpr int col_nt_c(int n, int kind) {
-  return (kind == 2 && n >= 384 && n <= 512) ? MBS_GREEN_NT : col_threads_c(n);
+  return green_tile_c(n, kind) ? (n < 384 ? MBS_GREEN_NT / 2 : MBS_GREEN_NT) : col_threads_c(n);
 }
 __host__ __device__ constexpr int col_wv_c(int n, int kind) {
-  return (kind == 2 && n >= 384 && n <= 512) ? MBS_GREEN_WAVES : col_waves_c(n);
+  return green_tile_c(n, kind) ? MBS_GREEN_WAVES : col_waves_c(n);
 }
 
 // N rows (the FFT axis) x WC contiguous columns, NTH threads; element (j, c) at j*WC + c.
@@ -609,7 +624,8 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
 // Persistent workgroups walk the tiles; the loads of the next tile are issued
 // before the LDS stages of the current one so that HBM traffic and LDS work overlap.
 // ---------------------------------------------------------------------------
-template <class Tile, int N, int R, int PER, bool FULL, class Ptr>
+// elements [FROM, TO) of the flattened (butterfly q, input m) order; the default is all of them
+template <class Tile, int N, int R, int PER, bool FULL, int FROM = 0, int TO = PER * R, class Ptr>
 __device__ __forceinline__ void load_cols(float2 (&v)[PER][R], Ptr tp, int stride, int ncols, int tid) {
   // tp: first element of the tile (uniform); per-lane offsets are 32-bit
 #pragma unroll
@@ -621,6 +637,7 @@ __device__ __forceinline__ void load_cols(float2 (&v)[PER][R], Ptr tp, int strid
     const int o0 = i * stride + c;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
+      if (q * R + m < FROM || q * R + m >= TO) continue;
       const int o = o0 + m * (N / R) * stride;
       if (FULL) v[q][m] = tp[o];
       else v[q][m] = in ? tp[o] : make_float2(0.f, 0.f);
@@ -678,7 +695,13 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
     const int nc0 = ncb * WC, nncols = min(WC, n2 - nc0);
     const int64_t nbase = more ? tile_base(nsub, nfx, ncb) : base;
     float2 nxt[PER0][R0];
-    if (MBS_COL_PREFETCH && more) load_cols<Tile, N, R0, PER0, FULL>(nxt, W + nbase, stride, nncols, tid);
+    // the next tile's loads are spread over the iteration (NSPL parts: before the FFT stages,
+    // then between them) so the memory pipe is not idle while the current tile computes
+    constexpr int NSPL = KIND == 2 ? MBS_GREEN_SPLIT : MBS_COL_SPLIT;
+    constexpr int E = PER0 * R0;
+    constexpr int P1 = NSPL >= 2 ? E / NSPL : E, P2 = NSPL >= 3 ? 2 * E / NSPL : E;
+    const bool pf = MBS_COL_PREFETCH && more;
+    if (pf) load_cols<Tile, N, R0, PER0, FULL, 0, P1>(nxt, W + nbase, stride, nncols, tid);
     keep_alive(o);
     if constexpr (KIND == 2) {
       float2 f[PERL][RL];
@@ -699,9 +722,22 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
           f[q][m] = cmul(f[q][m], make_float2(den, -E * den));
         }
       }
-      fft_tile<Tile, N, true, +1>(f, o, lds, s_tw, tid);
+      if (P1 < P2 && pf) load_cols<Tile, N, R0, PER0, FULL, P1, P2>(nxt, W + nbase, stride, nncols, tid);
+      fft_head<Tile, N, true, +1, PERL, RL>(f, lds, s_tw, tid);
+      if (P2 < E && pf) load_cols<Tile, N, R0, PER0, FULL, P2, E>(nxt, W + nbase, stride, nncols, tid);
+      fft_tail<Tile, N, true, +1, PERL, RL, PERO, RO>(f, o, lds, s_tw, tid);
     } else {
-      fft_tail<Tile, N, false, KIND == 1 ? +1 : -1, PER0, R0, PERL, RL>(cur, o, lds, s_tw, tid);
+      constexpr int PL = plan_len(N);
+      constexpr int SG = KIND == 1 ? +1 : -1;
+      if constexpr (PL > 1 && NSPL >= 2) {
+        lds_stages<Tile, N, false, SG, 1, PL - 1>(lds, s_tw, tid);
+        if (pf) load_cols<Tile, N, R0, PER0, FULL, P1, E>(nxt, W + nbase, stride, nncols, tid);
+        get_lds<Tile, N, RL, PERL>(lds, o, tid);
+        bfly_regs<Tile, N, RL, plan_ns(N, PL - 1, false), SG, PERL>(o, s_tw, tid);
+      } else {
+        fft_tail<Tile, N, false, SG, PER0, R0, PERL, RL>(cur, o, lds, s_tw, tid);
+        if (P1 < E && pf) load_cols<Tile, N, R0, PER0, FULL, P1, E>(nxt, W + nbase, stride, nncols, tid);
+      }
     }
 #pragma unroll
     for (int q = 0; q < PERO; ++q) {

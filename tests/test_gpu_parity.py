@@ -110,7 +110,7 @@ def test_separate_and_fused_z_passes_agree(shape, split, periodic, t):
     assert d <= 1e-5
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 8), (16, 12, 24), (96, 32, 64), (12, 192, 8), (384, 16, 32),
+@pytest.mark.parametrize("shape", [(8, 8, 8), (16, 12, 24), (96, 32, 64), (12, 192, 8), (256, 8, 32), (384, 16, 32),
                                    (512, 8, 16)])
 def test_plain_sizes_and_radices(shape):
     n, S = random_case(shape, seed=3, src="plane")
