@@ -31,9 +31,9 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {
     "workload": "dd1024",
     "fused": True,
-    "kernel_source_sha256": "7d826b208e876d30fcabf8aa3bc52e6e215b84d4dfeaf3eb5ce60b21c1d73efc",
+    "kernel_source_sha256": "9ba35c208d96b2797959867b6d4b9d76d406b257c49cfbcbb1bfbf2a7b772eea",
     "bytes": {"z_fwd": 2.137e9, "y_fwd": 17.180e9, "x_green": 17.180e9, "y_inv": 17.180e9,
-              "z_inv": 43.567e9, "edge_corr": 1.342e9, "face": 3.099e9},
+              "z_inv": 43.567e9, "edge_corr": 1.342e9, "face": 3.163e9},
 }
 METRIC = "MBS voxel-updates/s + HBM GB/s at 1024³; served solves/s and p99 latency"
 
