@@ -81,6 +81,14 @@ typedef struct {
                          /* residual; a solve that converges on the iterated set goes on if  */
                          /* some transfer still exceeds the threshold.  Needs the fused z    */
                          /* pass and at most 4096 subdomains (else MBS_EUNSUPPORTED).        */
+    int32_t zblock;      /* schedule of the three strided FFT passes (y, x with the Green    */
+                         /* multiply, inverse y): 0 = automatic, -1 = each pass over every   */
+                         /* subdomain in turn, > 0 = the three passes subdomain by subdomain */
+                         /* on slabs of zblock z values, so that a slab stays in the device's */
+                         /* memory-side cache between them (must divide n_2 and be a         */
+                         /* multiple of 16; fused z pass only, else MBS_EINVAL).  Results are */
+                         /* bitwise the same either way.                                     */
+    int32_t reserved;    /* 0                                                                  */
 } mbs_plan_desc;
 
 typedef struct {
@@ -152,7 +160,7 @@ mbs_status mbs_residual_history(mbs_plan plan, int32_t slot, double* host_out, i
  * 4 inverse pass with update (z), 5 edge corrections, 6 face update, 7 residual
  * reduction.  With the fused z pass, kind 4 also forms the next w and its forward z FFT,
  * kind 0 covers only the lines of the x/y edge slabs and kind 6 finishes those lines.
- * n_kinds <= 8. */
+ * Kind 8: kinds 1-3 run slab by slab (mbs_plan_desc.zblock), timed as one.  n_kinds <= 9. */
 mbs_status mbs_timing_read(mbs_plan plan, double* ms, int64_t* launches, int32_t n_kinds,
                            int32_t reset);
 

@@ -84,6 +84,12 @@ struct SlotDesc {
   int32_t pad;
 };
 
+// Part of a column pass: subdomains [sub0, sub0 + nsub) and z column chunks [cb0, cb0 + ncb) of
+// the pass's tile width; ncb <= 0 means the whole pass over every subdomain.
+struct ColRange {
+  int32_t sub0, nsub, cb0, ncb;
+};
+
 // Launch helpers implemented in mbs_kernels.hip.
 struct Tables {
   const float2* tw[3];    // forward twiddles exp(-2 pi i q / n_d), q < n_d
@@ -99,9 +105,10 @@ hipError_t launch_first_pass(const SlotDesc* tab, int nslots, const Geo& g, cons
 void prepare_launches(const Geo& g);
 hipError_t launch_xfer(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, hipStream_t s);
 hipError_t launch_mid_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
-                           int inverse, hipStream_t s);
+                           int inverse, hipStream_t s, ColRange rg = ColRange{0, 0, 0, 0});
 hipError_t launch_green_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
-                             hipStream_t s);
+                             hipStream_t s, ColRange rg = ColRange{0, 0, 0, 0});
+int col_chunk_width(int n, int kind);  // z columns per tile of a column pass
 hipError_t launch_last_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
                             hipStream_t s);
 hipError_t launch_corr(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, int which,

@@ -651,7 +651,7 @@ template <int N, int KIND, bool FULL, class Ptr>
 __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, int64_t tile, int64_t ntiles,
                                          float2* lds, const float2* s_tw, const float* s_p2x, const float* s_p2y,
                                          const float* s_p2z, float kb2, float cim, float inv,
-                                         const int32_t* act_list) {
+                                         const int32_t* act_list, ColRange rg) {
   constexpr int WC = col_wc_c(N, KIND);
   using Tile = ColTile<N, WC, col_nt_c(N, KIND)>;
   constexpr int P = plan_len(N);
@@ -659,7 +659,7 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
   constexpr int PER0 = per_thread<Tile, R0>(), PERL = per_thread<Tile, RL>();
   const int tid = threadIdx.x;
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
-  const int CB = (n2 + WC - 1) / WC;
+  const int CB = rg.ncb;  // column chunks walked: rg.cb0 .. rg.cb0 + rg.ncb - 1
   const int nfix = KIND == 2 ? n1 : n0;
   const int stride = KIND == 2 ? n1 * n2 : n2;
   // tile t = (s * nfix + fix) * CB + cb, walked with a stride of gridDim.x without divisions
@@ -669,11 +669,11 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
   // the walk runs over the iterated subdomains only (subdomain activation, Sec. 3.1): entry
   // s_ of the list, read with a scalar load so no vector load besides the tiles is in flight
   auto tile_base = [&](int s_, int fix_, int cb_) -> int64_t {
-    const int sid = act_list ? cp(act_list)[__builtin_amdgcn_readfirstlane(s_)] : s_;
-    return KIND == 2 ? ((int64_t)sid * N * n1 + fix_) * n2 + cb_ * WC
-                     : (((int64_t)sid * n0 + fix_) * N) * n2 + cb_ * WC;
+    const int sid = act_list ? cp(act_list)[__builtin_amdgcn_readfirstlane(s_)] : rg.sub0 + s_;
+    return KIND == 2 ? ((int64_t)sid * N * n1 + fix_) * n2 + (rg.cb0 + cb_) * WC
+                     : (((int64_t)sid * n0 + fix_) * N) * n2 + (rg.cb0 + cb_) * WC;
   };
-  int c0 = cb * WC, ncols = min(WC, n2 - c0);
+  int c0 = (rg.cb0 + cb) * WC, ncols = min(WC, n2 - c0);
   int64_t base = tile_base(sub, fix, cb);
   float2 cur[PER0][R0];
   load_cols<Tile, N, R0, PER0, FULL>(cur, W + base, stride, ncols, tid);
@@ -692,20 +692,31 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
     int ncb = cb + gcb, nfx = fix + gfix, nsub = sub + gsub;
     if (ncb >= CB) { ncb -= CB; ++nfx; }
     if (nfx >= nfix) { nfx -= nfix; ++nsub; }
-    const int nc0 = ncb * WC, nncols = min(WC, n2 - nc0);
+    const int nc0 = (rg.cb0 + ncb) * WC, nncols = min(WC, n2 - nc0);
     const int64_t nbase = more ? tile_base(nsub, nfx, ncb) : base;
     float2 nxt[PER0][R0];
     // the next tile's loads are spread over the iteration (NSPL parts: before the FFT stages,
     // then between them) so the memory pipe is not idle while the current tile computes
     constexpr int NSPL = KIND == 2 ? MBS_GREEN_SPLIT : MBS_COL_SPLIT;
     constexpr int E = PER0 * R0;
-    constexpr int P1 = NSPL >= 2 ? E / NSPL : E, P2 = NSPL >= 3 ? 2 * E / NSPL : E;
+    // part boundaries; the x pass with four parts also loads between its forward FFT stages
+    constexpr int Q4 = (KIND == 2 && NSPL >= 4) ? E / NSPL : 0;
+    constexpr int P1 = NSPL >= 2 ? Q4 + (E - Q4) / (NSPL - (Q4 ? 1 : 0)) : E;
+    constexpr int P2 = NSPL >= 3 ? P1 + (E - P1) / 2 : E;
     const bool pf = MBS_COL_PREFETCH && more;
-    if (pf) load_cols<Tile, N, R0, PER0, FULL, 0, P1>(nxt, W + nbase, stride, nncols, tid);
+    if (pf) load_cols<Tile, N, R0, PER0, FULL, 0, Q4 ? Q4 : P1>(nxt, W + nbase, stride, nncols, tid);
     keep_alive(o);
     if constexpr (KIND == 2) {
       float2 f[PERL][RL];
-      fft_tail<Tile, N, false, -1, PER0, R0, PERL, RL>(cur, f, lds, s_tw, tid);
+      constexpr int PL = plan_len(N);
+      if constexpr (Q4 > 0 && PL > 1) {
+        lds_stages<Tile, N, false, -1, 1, PL - 1>(lds, s_tw, tid);
+        if (pf) load_cols<Tile, N, R0, PER0, FULL, Q4, P1>(nxt, W + nbase, stride, nncols, tid);
+        get_lds<Tile, N, RL, PERL>(lds, f, tid);
+        bfly_regs<Tile, N, RL, plan_ns(N, PL - 1, false), -1, PERL>(f, s_tw, tid);
+      } else {
+        fft_tail<Tile, N, false, -1, PER0, R0, PERL, RL>(cur, f, lds, s_tw, tid);
+      }
       // (L + I)^-1 = 1 / (1 + c (k_b^2 - |p|^2)), c = i c_im, with the 1/(n0 n1 n2) of the inverse
       const float p21 = s_p2y[fix];
 #pragma unroll
@@ -769,10 +780,20 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
 
 template <int N, int KIND>
 __global__ __launch_bounds__(col_nt_c(N, KIND), col_wv_c(N, KIND)) void k_col(const SlotDesc* __restrict__ tab, Geo g,
-                                                                            Tables tb, int64_t ntiles) {
+                                                                            Tables tb, int64_t ntiles, ColRange rg) {
   const SlotDesc& sd = tab[blockIdx.y];
   if (sd.st->done != kRunning) return;
-  if (sd.act_list) ntiles = ntiles / g.S * sd.n_act;  // tiles of the iterated subdomains only
+  const int32_t* act_list = nullptr;
+  if (rg.nsub == g.S) {
+    // every subdomain: walk the iterated ones only (subdomain activation)
+    if (sd.act_list) ntiles = ntiles / g.S * sd.n_act;
+    act_list = sd.act_list;
+  } else if (sd.act) {
+    // a block of subdomains [sub0, sub0 + nsub): a launch for idle ones does nothing
+    bool any = false;
+    for (int q = 0; q < rg.nsub; ++q) any = any || sub_on(sd.act, rg.sub0 + q);
+    if (!any) return;
+  }
   int64_t tile = blockIdx.x;
   if (tile >= ntiles) return;
   constexpr int WC = col_wc_c(N, KIND);
@@ -802,9 +823,9 @@ __global__ __launch_bounds__(col_nt_c(N, KIND), col_wv_c(N, KIND)) void k_col(co
   const auto W = gp(sd.W);
   const float kb2 = sd.kb2, cim = sd.c_im, inv = sd.inv_vox;
   if (n2 % WC == 0)
-    col_loop<N, KIND, true>(W, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv, sd.act_list);
+    col_loop<N, KIND, true>(W, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv, act_list, rg);
   else
-    col_loop<N, KIND, false>(W, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv, sd.act_list);
+    col_loop<N, KIND, false>(W, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv, act_list, rg);
 }
 
 
@@ -1842,12 +1863,23 @@ static inline unsigned persistent_grid(int64_t ntiles, const Geo& g, int per_cu)
 }
 
 template <int NN, int KIND>
-static void launch_col(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, hipStream_t s) {
+static void launch_col(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, hipStream_t s,
+                       ColRange rg) {
   constexpr int WC = col_wc_c(NN, KIND);
   const int fix = KIND == 2 ? g.n[1] : g.n[0];
-  const int64_t ntiles = (int64_t)g.S * fix * ((g.n[2] + WC - 1) / WC);
+  if (rg.ncb <= 0) {
+    rg.sub0 = 0;
+    rg.nsub = g.S;
+    rg.cb0 = 0;
+    rg.ncb = (g.n[2] + WC - 1) / WC;
+  }
+  const int64_t ntiles = (int64_t)rg.nsub * fix * rg.ncb;
   dim3 grid(persistent_grid(ntiles, g, col_resident_per_cu<NN, KIND>()), nslots);
-  hipLaunchKernelGGL((k_col<NN, KIND>), grid, dim3(col_nt_c(NN, KIND)), 0, s, tab, g, tb, ntiles);
+  hipLaunchKernelGGL((k_col<NN, KIND>), grid, dim3(col_nt_c(NN, KIND)), 0, s, tab, g, tb, ntiles, rg);
+}
+
+int col_chunk_width(int n, int kind) {
+  return kind == 2 ? (n >= MBS_GREEN_MIN_N && n <= 512 ? MBS_GREEN_WC : cols_per_tile_c(n)) : cols_per_tile_c(n);
 }
 
 // occupancy queries of the plan's column kernels, made before any stream capture
@@ -1874,12 +1906,12 @@ void prepare_launches(const Geo& g) {
 }
 
 hipError_t launch_mid_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
-                           int inverse, hipStream_t s) {
+                           int inverse, hipStream_t s, ColRange rg) {
   switch (g.n[1]) {
-#define MBS_CASE(NN)                                          \
-  case NN:                                                    \
-    if (inverse) launch_col<NN, 1>(tab, nslots, g, tb, s);    \
-    else launch_col<NN, 0>(tab, nslots, g, tb, s);            \
+#define MBS_CASE(NN)                                              \
+  case NN:                                                        \
+    if (inverse) launch_col<NN, 1>(tab, nslots, g, tb, s, rg);    \
+    else launch_col<NN, 0>(tab, nslots, g, tb, s, rg);            \
     break;
     MBS_FOR_EACH_N(MBS_CASE)
 #undef MBS_CASE
@@ -1890,10 +1922,10 @@ hipError_t launch_mid_pass(const SlotDesc* tab, int nslots, const Geo& g, const 
 }
 
 hipError_t launch_green_pass(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb,
-                             hipStream_t s) {
+                             hipStream_t s, ColRange rg) {
   switch (g.n[0]) {
 #define MBS_CASE(NN) \
-  case NN: launch_col<NN, 2>(tab, nslots, g, tb, s); break;
+  case NN: launch_col<NN, 2>(tab, nslots, g, tb, s, rg); break;
     MBS_FOR_EACH_N(MBS_CASE)
 #undef MBS_CASE
     default:

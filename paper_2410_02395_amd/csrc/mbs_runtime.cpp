@@ -24,8 +24,8 @@ using namespace mbs;
 
 namespace {
 
-constexpr int kKinds = 8;
-enum Kind { kFirst = 0, kMidF = 1, kGreen = 2, kMidI = 3, kLast = 4, kCorr = 5, kFace = 6, kReduce = 7 };
+constexpr int kKinds = 9;
+enum Kind { kFirst = 0, kMidF = 1, kGreen = 2, kMidI = 3, kLast = 4, kCorr = 5, kFace = 6, kReduce = 7, kSlabs = 8 };
 
 // largest singular value of a small real matrix: sqrt of the largest eigenvalue of
 // M^T M by cyclic Jacobi rotations (FP64)
@@ -129,6 +129,7 @@ struct mbs_plan_s {
   bool timing = false;
   int64_t n_main = 0, n_face = 0;
   double activation = 0;    // > 0: subdomain activation with this threshold (relative to rho_ref)
+  int zblock = 0;           // > 0: column passes block by block of this many z values
   int act_words = 0;
   double* d_xfer = nullptr;       // nslots x S x kXferBlocks transfer partials
   double* h_xfer = nullptr;       // pinned, 2 x the above
@@ -179,12 +180,31 @@ namespace {
 
 bool valid_n(int n) { return n >= 8 && n <= 1024 && fft_size_supported(n); }
 
+// Memory-side cache (Infinity Cache) of the device, in bytes: 256 MB on MI355X.
+constexpr size_t kMallBytes = (size_t)256 << 20;
+
+// Slab height of the strided passes.  Automatic: when the work arrays of the plan exceed the
+// memory-side cache, the largest multiple of 16 dividing n_2 whose slab (n_0 n_1 z complex64
+// values of one subdomain) fits in it; otherwise every pass runs over every subdomain.
+int choose_zblock(const mbs_plan_desc* d, const Geo& g, bool fused) {
+  if (!fused || d->zblock < 0) return 0;
+  if (d->zblock > 0) return d->zblock;
+  const size_t plane = (size_t)g.n[0] * g.n[1] * sizeof(float2);
+  if ((size_t)g.S * g.sub_vox * sizeof(float2) * d->max_batch <= kMallBytes) return 0;
+  const int wy = col_chunk_width(g.n[1], 0), wx = col_chunk_width(g.n[0], 2);
+  for (int z = g.n[2]; z >= 16; --z)
+    if (g.n[2] % z == 0 && z % 16 == 0 && z % wy == 0 && z % wx == 0 && plane * z * d->max_batch <= kMallBytes)
+      return z;
+  return 0;
+}
+
 mbs_status validate(const mbs_plan_desc* d, Geo* g) {
   if (!d) return MBS_EINVAL;
   if (d->max_batch < 1 || d->max_batch > 4096) return MBS_EINVAL;
   if (!(d->alpha > 0.0 && d->alpha <= 1.0)) return MBS_EINVAL;
   if (d->check_every < 0) return MBS_EINVAL;
   if (!(d->activation >= 0.0 && std::isfinite(d->activation))) return MBS_EINVAL;
+  if (d->zblock < -1 || d->reserved != 0) return MBS_EINVAL;
   Geo geo{};
   int64_t sub = 1, vox = 1;
   int S = 1;
@@ -232,6 +252,14 @@ mbs_status validate(const mbs_plan_desc* d, Geo* g) {
       geo.reg_count[r] = (int64_t)geo.reg_ext[r][0] * geo.reg_ext[r][1] * geo.reg_ext[r][2];
       geo.face_vox += geo.reg_count[r];
     }
+  }
+  if (d->zblock > 0) {
+    // slabs of the strided passes: whole tiles of both column kinds, fused sequence only
+    const int n2 = geo.n[2];
+    if (n2 % d->zblock != 0 || d->zblock % col_chunk_width(geo.n[1], 0) != 0 ||
+        d->zblock % col_chunk_width(geo.n[0], 2) != 0 || d->zblock % 16 != 0)
+      return MBS_EINVAL;
+    if ((d->flags & MBS_NO_FUSION) || !fusion_supported(geo)) return MBS_EINVAL;
   }
   if (d->activation > 0.0) {
     // activation skips whole subdomains of the fused z-pass sequence
@@ -391,15 +419,32 @@ hipError_t enqueue_iteration(mbs_plan p, const SlotDesc* tab, int nslots, hipStr
     }
   };
   hipError_t e;
-  rec(kMidF, true);
-  if ((e = launch_mid_pass(tab, nslots, g, p->tb, 0, s)) != hipSuccess) return e;
-  rec(kMidF, false);
-  rec(kGreen, true);
-  if ((e = launch_green_pass(tab, nslots, g, p->tb, s)) != hipSuccess) return e;
-  rec(kGreen, false);
-  rec(kMidI, true);
-  if ((e = launch_mid_pass(tab, nslots, g, p->tb, 1, s)) != hipSuccess) return e;
-  rec(kMidI, false);
+  if (p->zblock > 0) {
+    // the three column passes block by block (one subdomain, zblock z values: a working set
+    // that stays in the memory-side cache between the passes)
+    // one timing record for the whole slab sequence (events between its many short launches
+    // would add gaps of their own)
+    const int wy = col_chunk_width(g.n[1], 0), wx = col_chunk_width(g.n[0], 2);
+    rec(kSlabs, true);
+    for (int sub = 0; sub < g.S; ++sub)
+      for (int z0 = 0; z0 < g.n[2]; z0 += p->zblock) {
+        const ColRange ry{sub, 1, z0 / wy, p->zblock / wy}, rx{sub, 1, z0 / wx, p->zblock / wx};
+        if ((e = launch_mid_pass(tab, nslots, g, p->tb, 0, s, ry)) != hipSuccess) return e;
+        if ((e = launch_green_pass(tab, nslots, g, p->tb, s, rx)) != hipSuccess) return e;
+        if ((e = launch_mid_pass(tab, nslots, g, p->tb, 1, s, ry)) != hipSuccess) return e;
+      }
+    rec(kSlabs, false);
+  } else {
+    rec(kMidF, true);
+    if ((e = launch_mid_pass(tab, nslots, g, p->tb, 0, s)) != hipSuccess) return e;
+    rec(kMidF, false);
+    rec(kGreen, true);
+    if ((e = launch_green_pass(tab, nslots, g, p->tb, s)) != hipSuccess) return e;
+    rec(kGreen, false);
+    rec(kMidI, true);
+    if ((e = launch_mid_pass(tab, nslots, g, p->tb, 1, s)) != hipSuccess) return e;
+    rec(kMidI, false);
+  }
   rec(kLast, true);
   if ((e = launch_fused(tab, nslots, g, p->tb, s)) != hipSuccess) return e;
   rec(kLast, false);
@@ -886,6 +931,7 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
   p->corr01 = g.a[0] || g.a[1];
   p->fused = !(desc->flags & MBS_NO_FUSION) && fusion_supported(g);
   p->activation = desc->activation;
+  p->zblock = choose_zblock(desc, g, p->fused);
   p->check_every = desc->check_every > 0 ? desc->check_every : 16;
   p->timing = (desc->flags & MBS_TIMING) != 0;
   p->use_graph = !(desc->flags & (MBS_NO_GRAPH | MBS_TIMING));

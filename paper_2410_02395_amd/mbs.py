@@ -43,8 +43,8 @@ MBS_NO_FUSION = 0x10
 
 # kernel kinds of mbs_timing_read, in order (with the fused z pass, "z_fwd" covers only the
 # x/y edge-slab lines, "z_inv" also forms and transforms the next w, "face" finishes the
-# edge-slab lines)
-KERNEL_KINDS = ("z_fwd", "y_fwd", "x_green", "y_inv", "z_inv", "edge_corr", "face", "reduce")
+# edge-slab lines; "yxy_slabs" is the y, x and inverse-y passes run slab by slab)
+KERNEL_KINDS = ("z_fwd", "y_fwd", "x_green", "y_inv", "z_inv", "edge_corr", "face", "reduce", "yxy_slabs")
 
 
 class PlanDesc(ctypes.Structure):
@@ -58,6 +58,8 @@ class PlanDesc(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("check_every", ctypes.c_int32),
         ("activation", ctypes.c_double),
+        ("zblock", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -131,7 +133,7 @@ def _check(status: int, what: str):
 
 
 def make_desc(shape, split=(1, 1, 1), periodic=(1, 1, 1), t=8, max_batch=1, alpha=0.75,
-              flags=0, check_every=0, activation=0.0) -> PlanDesc:
+              flags=0, check_every=0, activation=0.0, zblock=0) -> PlanDesc:
     d = PlanDesc()
     for k in range(3):
         d.shape[k] = int(shape[k])
@@ -143,15 +145,18 @@ def make_desc(shape, split=(1, 1, 1), periodic=(1, 1, 1), t=8, max_batch=1, alph
     d.flags = int(flags)
     d.check_every = int(check_every)
     d.activation = float(activation)
+    d.zblock = int(zblock)
+    d.reserved = 0
     return d
 
 
 def plan_bytes(shape, split=(1, 1, 1), periodic=(1, 1, 1), t=8, max_batch=1, alpha=0.75,
-               flags=0, check_every=0, activation=0.0) -> int:
+               flags=0, check_every=0, activation=0.0, zblock=0) -> int:
     lib = load_library()
     out = ctypes.c_size_t(0)
     _check(lib.mbs_plan_bytes(ctypes.byref(make_desc(shape, split, periodic, t, max_batch, alpha,
-                                                     flags, check_every, activation)), ctypes.byref(out)),
+                                                     flags, check_every, activation, zblock)),
+                              ctypes.byref(out)),
            "mbs_plan_bytes")
     return int(out.value)
 
@@ -168,7 +173,8 @@ class Plan:
     """One solver plan (grid, decomposition, slots) on the current device."""
 
     def __init__(self, shape, split=(1, 1, 1), periodic=(1, 1, 1), t=8, max_batch=1, alpha=0.75,
-                 flags=0, check_every=0, stream: Optional[torch.cuda.Stream] = None, activation=0.0):
+                 flags=0, check_every=0, stream: Optional[torch.cuda.Stream] = None, activation=0.0,
+                 zblock=0):
         self._lib = load_library()
         self.shape = tuple(int(s) for s in shape)
         self.split = tuple(int(s) for s in split)
@@ -179,7 +185,8 @@ class Plan:
         self.flags = int(flags)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.activation = float(activation)
-        self._desc = make_desc(shape, split, periodic, t, max_batch, alpha, flags, check_every, activation)
+        self._desc = make_desc(shape, split, periodic, t, max_batch, alpha, flags, check_every, activation,
+                               zblock)
         h = ctypes.c_void_p(0)
         _check(self._lib.mbs_plan_create(ctypes.byref(self._desc), ctypes.c_void_p(self.stream.cuda_stream),
                                          ctypes.byref(h)), "mbs_plan_create")
@@ -259,7 +266,8 @@ class Plan:
         return [buf[i] for i in range(n.value)]
 
     def timing(self, reset: bool = False) -> dict:
-        ms = (ctypes.c_double * 8)()
-        cnt = (ctypes.c_int64 * 8)()
-        _check(self._lib.mbs_timing_read(self._h, ms, cnt, 8, int(reset)), "mbs_timing_read")
+        nk = len(KERNEL_KINDS)
+        ms = (ctypes.c_double * nk)()
+        cnt = (ctypes.c_int64 * nk)()
+        _check(self._lib.mbs_timing_read(self._h, ms, cnt, nk, int(reset)), "mbs_timing_read")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS)}

@@ -83,7 +83,7 @@ def test_struct_layouts_match_header(mbs_mod, tmp_path):
 
 
 def _desc(mbs, shape=(64, 64, 64), split=(1, 1, 1), periodic=(1, 1, 1), t=8, max_batch=1, alpha=0.75,
-          check_every=0, flags=0, activation=0.0):
+          check_every=0, flags=0, activation=0.0, zblock=0, reserved=0):
     d = mbs.PlanDesc()
     d.shape[:] = shape
     d.split[:] = split
@@ -94,6 +94,8 @@ def _desc(mbs, shape=(64, 64, 64), split=(1, 1, 1), periodic=(1, 1, 1), t=8, max
     d.flags = flags
     d.check_every = check_every
     d.activation = activation
+    d.zblock = zblock
+    d.reserved = reserved
     return d
 
 
@@ -143,10 +145,23 @@ def test_plan_bytes_memory_model(mbs_mod, lib):
      "MBS_EUNSUPPORTED"),
     (dict(shape=(512, 512, 16), split=(64, 64, 2), periodic=(0, 0, 0), t=4, activation=1e-4),
      "MBS_EUNSUPPORTED"),
+    # z slabs of the strided passes: multiples of 16 (and of the tile width) dividing n_2
+    (dict(zblock=-2), "MBS_EINVAL"),
+    (dict(shape=(256, 256, 128), zblock=24), "MBS_EINVAL"),
+    (dict(shape=(256, 256, 96), zblock=64), "MBS_EINVAL"),
+    (dict(shape=(64, 64, 64), zblock=16), "MBS_EINVAL"),      # 64-point y pass: 32-column tiles
+    (dict(shape=(256, 256, 128), zblock=32, flags=0x10), "MBS_EINVAL"),
+    (dict(reserved=1), "MBS_EINVAL"),
 ])
 def test_plan_bytes_rejects_what_plan_create_rejects(mbs_mod, lib, kw, status):
     st, _ = _bytes(mbs_mod, lib, **kw)
     assert st == getattr(mbs_mod, status)
+
+
+def test_slab_heights_that_are_accepted(mbs_mod, lib):
+    for zb in (-1, 0, 16, 32, 64, 128):
+        st, _ = _bytes(mbs_mod, lib, shape=(256, 256, 128), zblock=zb)
+        assert st == mbs_mod.MBS_OK, zb
 
 
 def test_plan_bytes_with_activation(mbs_mod, lib):

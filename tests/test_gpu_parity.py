@@ -202,3 +202,26 @@ def test_error_paths():
         assert e.value.status == mbs.MBS_ENONFINITE
         _, r = plan.solve(0, S, 1e-12, 3)          # not converging is not an error
         assert r["iterations"] == 3 and r["converged"] == 0
+
+
+def test_slab_schedule_of_the_strided_passes_is_bitwise_neutral():
+    """The y, x and inverse-y passes run pass by pass over every subdomain, or subdomain by
+    subdomain on z slabs (zblock): each tile computes the same values either way."""
+    from paper_2410_02395_amd import mbs
+    import torch
+    shape, split, periodic, t = (256, 256, 128), (2, 2, 2), (0, 0, 0), 8
+    n, S = random_case(shape, seed=13)
+    k = 2 * math.pi / 4
+    dev = torch.device("cuda:0")
+    nt = torch.from_numpy(n).to(dev)
+    St = torch.from_numpy(S).to(dev)
+    outs = {}
+    for zb in (-1, 32, 64):
+        for act in (0.0, 1e-2):
+            with mbs.Plan(shape, split, periodic, t, 1, 0.75, 0, 8, activation=act, zblock=zb) as plan:
+                plan.set_medium(0, nt, k, (4, 4, 4), 0.2)
+                out, res = plan.solve(0, St, 0.0, 24)
+                outs[(zb, act)] = out.cpu().numpy()
+    for act in (0.0, 1e-2):
+        assert np.array_equal(outs[(-1, act)], outs[(32, act)])
+        assert np.array_equal(outs[(-1, act)], outs[(64, act)])
