@@ -31,9 +31,9 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {
     "workload": "dd1024",
     "fused": True,
-    "kernel_source_sha256": "9ba35c208d96b2797959867b6d4b9d76d406b257c49cfbcbb1bfbf2a7b772eea",
-    "bytes": {"z_fwd": 2.137e9, "y_fwd": 17.180e9, "x_green": 17.180e9, "y_inv": 17.180e9,
-              "z_inv": 43.567e9, "edge_corr": 1.342e9, "face": 3.163e9},
+    "kernel_source_sha256": "9976a8a49c644503eebde0911a160c51f4e7597491e9f8a31ba6da86207af914",
+    "bytes": {"z_fwd": 2.137e9, "yxy_slabs": 51.55e9, "z_inv": 43.567e9, "edge_corr": 2.684e9,
+              "face": 3.158e9},
 }
 METRIC = "MBS voxel-updates/s + HBM GB/s at 1024³; served solves/s and p99 latency"
 
