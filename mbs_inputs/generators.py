@@ -160,6 +160,13 @@ WORKLOADS: Dict[str, Workload] = {
         0.75, 1e-4, 20000,
         medium=dict(kind="random", seed=3, n_min=1.0, n_max=1.5),
         source=dict(kind="beam", z=20, waist_wavelengths=8.0)),
+    # 1024^3 as one domain (periodic axes with 32-voxel ramps), the same medium recipe and
+    # source as dd1024: the undecomposed case for context
+    "plain1024": Workload(
+        "plain1024", (1024, 1024, 1024), (1, 1, 1), (1, 1, 1), 8, 4.0, (32, 32, 32), 0.2,
+        0.75, 1e-4, 200,
+        medium=dict(kind="random", seed=4, n_min=1.0, n_max=1.5),
+        source=dict(kind="plane", z=40)),
     # 1024^3 as 2x2x2 subdomains of 512^3; planar source; 32-voxel ramps
     "dd1024": Workload(
         "dd1024", (1024, 1024, 1024), (2, 2, 2), (0, 0, 0), 8, 4.0, (32, 32, 32), 0.2,

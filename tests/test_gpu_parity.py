@@ -95,6 +95,7 @@ def test_decomposed_fixed_iterations(shape, split, periodic, t):
     ((64, 64, 64), (2, 2, 2), (0, 0, 0), 8),
     ((48, 24, 96), (2, 1, 2), (1, 0, 0), 4),
     ((16, 24, 144), (1, 1, 3), (1, 1, 1), 4),    # three segments on a cyclic z axis
+    ((16, 16, 2048), (1, 1, 2), (0, 0, 0), 8),   # two 1024-point segments per workgroup
 ])
 def test_separate_and_fused_z_passes_agree(shape, split, periodic, t):
     """The two launch sequences (the inverse z pass of one iteration fused with the
@@ -111,7 +112,8 @@ def test_separate_and_fused_z_passes_agree(shape, split, periodic, t):
 
 
 @pytest.mark.parametrize("shape", [(8, 8, 8), (16, 12, 24), (96, 32, 64), (12, 192, 8), (256, 8, 32), (384, 16, 32),
-                                   (512, 8, 16)])
+                                   (512, 8, 16), (768, 8, 16), (1024, 8, 16), (8, 768, 16), (8, 1024, 16),
+                                   (16, 8, 768), (16, 8, 1024)])
 def test_plain_sizes_and_radices(shape):
     n, S = random_case(shape, seed=3, src="plane")
     _compare(shape, (1, 1, 1), (1, 1, 1), 8, n, S, 2 * math.pi / 5, (2, 2, 2), 0.3, 40)
