@@ -216,7 +216,19 @@ def tolerance_study(args, w, n, S, mbs):
         out = torch.empty(w.shape, dtype=torch.complex64, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, res = plan.solve(0, S, args.tol, 100000, out=out)
+        plan.solve_async(0, S, args.tol, args.max_iter, out)
+        last = t0
+        while True:
+            res = plan.poll(0)
+            if res is not None:
+                break
+            now = time.perf_counter()
+            if now - last > 20.0:  # a long solve reports how far it has come
+                it, eps = plan.progress.get(0, (0, 0.0))
+                print(f"[bench] {name}: iteration {it}, residual {eps:.3e}, {now - t0:.0f} s",
+                      file=sys.stderr, flush=True)
+                last = now
+            time.sleep(0.002)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         full = plan.residual(0, out)
@@ -266,6 +278,7 @@ def main():
     ap.add_argument("--tol", type=float, default=0.0,
                     help="solve the workload to this relative residual, with and without subdomain "
                          "activation, and report iterations and wall time instead of the fixed-count run")
+    ap.add_argument("--max-iter", type=int, default=100000, help="iteration cap of the --tol study")
     ap.add_argument("--activation", default="1e-3",
                     help="comma-separated activation thresholds (relative to ||Gamma^-1 y||) of the "
                          "--tol study")

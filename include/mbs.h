@@ -138,8 +138,9 @@ mbs_status mbs_solve(mbs_plan plan, int32_t slot, const void* src_dev, double to
                      int32_t max_iter, void* field_dev, mbs_result* res);
 
 /* Start a solve and return at once; several slots of one plan iterate together in batched
- * launches.  mbs_poll advances the plan and returns MBS_EBUSY until the slot has finished,
- * then MBS_OK (field written, *res filled) or the solve's error. */
+ * launches.  mbs_poll advances the plan and returns MBS_EBUSY until the slot has finished
+ * (then res, if given, holds the progress: iterations and rel_residual as of the last completed
+ * launch, status MBS_EBUSY), then MBS_OK (field written, *res filled) or the solve's error. */
 mbs_status mbs_solve_async(mbs_plan plan, int32_t slot, const void* src_dev, double tol,
                            int32_t max_iter, void* field_dev);
 mbs_status mbs_poll(mbs_plan plan, int32_t slot, mbs_result* res);

@@ -108,7 +108,8 @@ struct Slot {
   std::vector<uint32_t> act_h;    // host copy of the mask
   int32_t n_act = 0;
   int64_t sub_iters = 0;          // sum over iterations of the subdomains iterated
-  int32_t iter_seen = 0;          // iterations accounted in sub_iters
+  int32_t iter_seen = 0;          // iterations accounted in sub_iters (progress of a running solve)
+  double eps_seen = 0;            // relative residual of the last iteration seen by the host
 };
 
 }  // namespace
@@ -119,6 +120,8 @@ struct mbs_plan_s {
   int device = 0;
   hipStream_t stream = nullptr;   // caller's stream
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+  hipStream_t side_stream = nullptr; // second stream of the slab schedule (every other slab)
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int nslots = 0;
   bool corr = false;
   bool fused = false;       // fused z passes (last inverse + next forward)
@@ -182,6 +185,11 @@ bool valid_n(int n) { return n >= 8 && n <= 1024 && fft_size_supported(n); }
 
 // Memory-side cache (Infinity Cache) of the device, in bytes: 256 MB on MI355X.
 constexpr size_t kMallBytes = (size_t)256 << 20;
+// streams the slabs of the strided passes alternate over (2: each slab's working set is then
+// half the cache)
+#ifndef MBS_SLAB_STREAMS
+#define MBS_SLAB_STREAMS 1
+#endif
 
 // Slab height of the strided passes.  Automatic: when the work arrays of the plan exceed the
 // memory-side cache, the largest multiple of 16 dividing n_2 whose slab (n_0 n_1 z complex64
@@ -193,7 +201,8 @@ int choose_zblock(const mbs_plan_desc* d, const Geo& g, bool fused) {
   if ((size_t)g.S * g.sub_vox * sizeof(float2) * d->max_batch <= kMallBytes) return 0;
   const int wy = col_chunk_width(g.n[1], 0), wx = col_chunk_width(g.n[0], 2);
   for (int z = g.n[2]; z >= 16; --z)
-    if (g.n[2] % z == 0 && z % 16 == 0 && z % wy == 0 && z % wx == 0 && plane * z * d->max_batch <= kMallBytes)
+    if (g.n[2] % z == 0 && z % 16 == 0 && z % wy == 0 && z % wx == 0 &&
+        plane * z * d->max_batch * MBS_SLAB_STREAMS <= kMallBytes)
       return z;
   return 0;
 }
@@ -426,13 +435,26 @@ hipError_t enqueue_iteration(mbs_plan p, const SlotDesc* tab, int nslots, hipStr
     // would add gaps of their own)
     const int wy = col_chunk_width(g.n[1], 0), wx = col_chunk_width(g.n[0], 2);
     rec(kSlabs, true);
+    // with a side stream, every other slab runs there: the slabs are independent, so one slab's
+    // passes overlap the start and the tail of the other's
+    const bool two = p->side_stream != nullptr;
+    if (two) {
+      if ((e = hipEventRecord(p->fork_ev, s)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(p->side_stream, p->fork_ev, 0)) != hipSuccess) return e;
+    }
+    int k = 0;
     for (int sub = 0; sub < g.S; ++sub)
-      for (int z0 = 0; z0 < g.n[2]; z0 += p->zblock) {
+      for (int z0 = 0; z0 < g.n[2]; z0 += p->zblock, ++k) {
         const ColRange ry{sub, 1, z0 / wy, p->zblock / wy}, rx{sub, 1, z0 / wx, p->zblock / wx};
-        if ((e = launch_mid_pass(tab, nslots, g, p->tb, 0, s, ry)) != hipSuccess) return e;
-        if ((e = launch_green_pass(tab, nslots, g, p->tb, s, rx)) != hipSuccess) return e;
-        if ((e = launch_mid_pass(tab, nslots, g, p->tb, 1, s, ry)) != hipSuccess) return e;
+        hipStream_t st = (two && (k & 1)) ? p->side_stream : s;
+        if ((e = launch_mid_pass(tab, nslots, g, p->tb, 0, st, ry)) != hipSuccess) return e;
+        if ((e = launch_green_pass(tab, nslots, g, p->tb, st, rx)) != hipSuccess) return e;
+        if ((e = launch_mid_pass(tab, nslots, g, p->tb, 1, st, ry)) != hipSuccess) return e;
       }
+    if (two) {
+      if ((e = hipEventRecord(p->join_ev, p->side_stream)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(s, p->join_ev, 0)) != hipSuccess) return e;
+    }
     rec(kSlabs, false);
   } else {
     rec(kMidF, true);
@@ -690,6 +712,7 @@ mbs_status progress(mbs_plan p, bool block) {
       const int32_t n_set = p->activation > 0.0 ? s.n_act : p->geo.S;
       s.sub_iters += (int64_t)(hs[i].iter - s.iter_seen) * n_set;
       s.iter_seen = hs[i].iter;
+      s.eps_seen = hs[i].eps;
     }
     if (p->activation > 0.0) {
       const size_t nx = (size_t)p->nslots * p->geo.S * kXferBlocks;
@@ -831,6 +854,7 @@ mbs_status start_solve(mbs_plan p, int slot, const void* src, double tol, int32_
   s.busy = true;
   s.sub_iters = 0;
   s.iter_seen = 0;
+  s.eps_seen = 0;
   s.start_seq = p->chunk_seq;
   s.finishing = false;
   s.field_out = field;
@@ -900,6 +924,9 @@ mbs_status mbs_plan_destroy(mbs_plan p) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
+  if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+  if (p->join_ev) (void)hipEventDestroy(p->join_ev);
   if (p->chunk_ev) (void)hipEventDestroy(p->chunk_ev);
   for (auto& s : p->slots)
     if (s.done_ev) (void)hipEventDestroy(s.done_ev);
@@ -949,6 +976,11 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
   }
   prepare_launches(p->geo);
   if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(MBS_EHIP);
+  if (p->zblock > 0 && MBS_SLAB_STREAMS > 1) {
+    if (hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking) != hipSuccess) return fail(MBS_EHIP);
+    if (hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming) != hipSuccess) return fail(MBS_EHIP);
+    if (hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming) != hipSuccess) return fail(MBS_EHIP);
+  }
   if (hipEventCreateWithFlags(&p->chunk_ev, hipEventDisableTiming) != hipSuccess) return fail(MBS_EHIP);
   // tables: twiddles, |p|^2 per axis, correction block (FP64 on the host, rounded once)
   for (int d = 0; d < 3; ++d) {
@@ -1112,7 +1144,16 @@ mbs_status mbs_poll(mbs_plan p, int32_t slot, mbs_result* res) {
   if (!p || slot < 0 || slot >= p->nslots) return MBS_EINVAL;
   mbs_status st = progress(p, false);
   if (st != MBS_OK) return st;
-  return finish_poll(p, slot, res);
+  st = finish_poll(p, slot, res);
+  if (st == MBS_EBUSY && res) {
+    // progress of the running solve, as of the last completed launch
+    const Slot& s = p->slots[slot];
+    *res = mbs_result{};
+    res->iterations = s.iter_seen;
+    res->rel_residual = s.eps_seen;
+    res->status = MBS_EBUSY;
+  }
+  return st;
 }
 
 mbs_status mbs_solve(mbs_plan p, int32_t slot, const void* src_dev, double tol, int32_t max_iter,

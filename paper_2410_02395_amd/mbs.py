@@ -192,6 +192,7 @@ class Plan:
                                          ctypes.byref(h)), "mbs_plan_create")
         self._h = h
         self._keep = {}
+        self.progress = {}
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -243,10 +244,13 @@ class Plan:
         self._keep[slot] = (S, out)
 
     def poll(self, slot: int):
-        """None while the slot is running, else its result dict (raises on a solve error)."""
+        """None while the slot is running (``self.progress[slot]`` then holds the iterations and
+        relative residual of its last completed launch), else its result dict (raises on a solve
+        error)."""
         res = Result()
         st = self._lib.mbs_poll(self._h, int(slot), ctypes.byref(res))
         if st == MBS_EBUSY:
+            self.progress[int(slot)] = (res.iterations, res.rel_residual)
             return None
         self._keep.pop(slot, None)
         _check(st, "mbs_poll")
