@@ -199,6 +199,39 @@ def serving_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def stream_ceilings():
+    """HBM rates of plain streaming torch kernels over 8 GiB complex64 arrays (best of 4)."""
+    import torch
+    dev = torch.device("cuda:0")
+    n = 1 << 30
+    a = torch.ones(n, dtype=torch.complex64, device=dev)
+    b = torch.ones(n, dtype=torch.complex64, device=dev)
+    c = torch.ones(n, dtype=torch.complex64, device=dev)
+    d = torch.empty(n, dtype=torch.complex64, device=dev)
+    ar, br, cr, dr = (torch.view_as_real(t) for t in (a, b, c, d))
+    cases = {
+        "read": (lambda: torch.sum(ar), 8 * n),
+        "write": (lambda: d.fill_(1.0), 8 * n),
+        "copy (read 1, write 1)": (lambda: d.copy_(a), 16 * n),
+        "addcmul (read 3, write 1)": (lambda: torch.addcmul(ar, br, cr, out=dr), 32 * n),
+    }
+    out = {}
+    for name, (fn, nbytes) in cases.items():
+        best = None
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None or ms < best else best
+        out[name] = {"ms": round(best, 4), "gbps": round(nbytes / (best * 1e-3) / 1e9, 1)}
+        print(f"[bench] {name}: {out[name]}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "HBM streaming ceilings (8 GiB complex64 arrays)", "unit": "GB/s",
+                      "results": out}), flush=True)
+
+
 def tolerance_study(args, w, n, S, mbs):
     """Solve to a tolerance with every subdomain iterated and with subdomain activation
     (Sec. 3.1) at each threshold: iterations, subdomain-iterations, wall time, the full
@@ -268,6 +301,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--stream-ceilings", action="store_true",
+                    help="only measure plain streaming kernels over 8 GiB arrays (read, write, copy, "
+                         "3 reads + 1 write): the HBM rates the iteration's byte mixes can reach")
     ap.add_argument("--serving", action="store_true",
                     help="run the mixed-size request-stream benchmark instead of the 1024^3 iteration")
     ap.add_argument("--requests", type=int, default=200)
@@ -294,6 +330,9 @@ def main():
 
     if args.serving:
         serving_bench(args)
+        return
+    if args.stream_ceilings:
+        stream_ceilings()
         return
 
     w = workload(args.workload)
