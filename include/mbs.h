@@ -55,7 +55,8 @@ typedef int32_t mbs_status;
 #define MBS_KB_FROM_K0 0x1u  /* k_b^2 = k0^2 instead of the midpoint of Re k^2          */
 #define MBS_X0_GIVEN 0x2u    /* mbs_solve reads the starting field from field_dev       */
 #define MBS_NO_GRAPH 0x4u    /* launch kernels one by one instead of as hipGraphs       */
-#define MBS_TIMING 0x8u      /* record HIP events around every kernel (implies no graph)*/
+#define MBS_TIMING 0x8u      /* record HIP events around every kernel kind (implies no  */
+                             /* graph; the slab sequence of the strided passes as one)  */
 #define MBS_NO_FUSION 0x10u  /* keep the last inverse and the next first forward z pass  */
                              /* separate (the fused pass is the default when the         */
                              /* subdomains along z fit one workgroup's line tile)        */

@@ -1,20 +1,24 @@
 // HIP kernels (gfx950) of the modified Born series iteration with domain
 // decomposition (Mache & Vellekoop, arXiv 2410.02395).
 //
-// One iteration of Eq. 6 on every subdomain of every active slot:
-//   corr(X)  edge corrections of the iterate             (Sec. 3.1 steps 1-2)
-//   first    w = y + B x + Ex, FFT along z               (Eq. 6 inner (I-V)x, Eq. 5)
-//   mid      FFT along y
-//   green    FFT along x, multiply by (L+I)^-1 symbol, inverse FFT along x
-//   mid      inverse FFT along y
-//   last     inverse FFT along z, u = x - v, x -= alpha B u  (Eq. 6 outer)
-//   corr(U)  edge corrections of u
-//   face     finish x and the residual on the edge slabs (Sec. 3.1 steps 3-5)
-//   reduce   rho_n = ||d_n|| in FP64, eps_n, stop test    (Sec. 3.1 stop rule)
-// The FFTs are Stockham autosort passes (radix 8/4/3/2) over tiles staged in
-// LDS: whole lines along the contiguous axis, or N x WC column tiles along a
-// strided axis, so every global access is a coalesced row of >= 64 bytes.
-// No MFMA: nothing here is a dense contraction; the path is HBM-bound.
+// One iteration of Eq. 6 on every subdomain of every active slot (default sequence):
+//   k_col<.,0>  FFT along y of w                           (Eq. 5)
+//   k_col<.,2>  FFT along x, multiply by the (L+I)^-1 symbol, inverse FFT along x
+//   k_col<.,1>  inverse FFT along y
+//               (the three column passes run whole, or subdomain by subdomain on z slabs
+//               that stay in the memory-side cache between them)
+//   k_fused     per global z-line: inverse FFT along z, u = x - v, d = B u + z-edge terms,
+//               x -= alpha d, FP64 residual partials; then w of the next iteration,
+//               y + B x + z-edge terms, and its forward FFT along z  (Eq. 6, Sec. 3.1)
+//   k_corr      x/y edge corrections of u; k_slabA finishes the x/y edge-slab lines
+//   k_corr      x/y edge corrections of the new x; k_wpass forms w on the edge-slab lines
+//   reduce      rho_n = ||d_n|| in FP64, eps_n, stop test  (Sec. 3.1 stop rule)
+// A separate sequence (k_first, k_last, k_face: first forward and last inverse z pass
+// apart) serves plans that do not fuse and the residual evaluation.  The FFTs are
+// Stockham autosort passes (radix 8/4/3/2) over tiles staged in LDS: whole lines along
+// the contiguous axis, or N x WC column tiles along a strided axis, so every global
+// access is a coalesced row of >= 64 bytes.  No MFMA: nothing here is a dense
+// contraction; the path is HBM-bound.
 
 #include <hip/hip_runtime.h>
 #include <math.h>

@@ -6,7 +6,9 @@
 // axis, the source on its bounding box and the FP64 residual partials.  The
 // FP64 scalars of Eq. 9 (k_b^2, ||k^2 - k_b^2||_inf, ||A12||, c) live on the
 // host.  Iterations are enqueued as hipGraphs of `check_every` iterations over
-// all slots; a slot whose device stop flag is set skips every kernel.
+// all slots; a slot whose device stop flag is set skips every kernel.  Between
+// graph launches the host collects finished slots and, for plans with subdomain
+// activation, lets idle subdomains join.
 
 #include <hip/hip_runtime.h>
 
