@@ -88,7 +88,9 @@ typedef struct {
                          /* on slabs of zblock z values, so that a slab stays in the device's */
                          /* memory-side cache between them (must divide n_2 and be a         */
                          /* multiple of 16; fused z pass only, else MBS_EINVAL).  Results are */
-                         /* bitwise the same either way.                                     */
+                         /* bitwise the same either way.  With slabs, n_2 and zblock powers   */
+                         /* of two and zblock < n_2, the work array is stored slab by slab    */
+                         /* and the plan keeps one more complex64 array per voxel.           */
     int32_t reserved;    /* 0                                                                  */
 } mbs_plan_desc;
 
@@ -114,8 +116,9 @@ typedef struct {
 } mbs_result;
 
 /* Device bytes a plan with this descriptor allocates (all slots), for HBM-budget admission
- * (Sec. 3.3 gives the paper's memory model; this plan keeps 3 complex64 arrays per voxel plus
- * edge buffers).  Returns MBS_EINVAL/MBS_EUNSUPPORTED for descriptors mbs_plan_create rejects. */
+ * (Sec. 3.3 gives the paper's memory model; this plan keeps 3 complex64 arrays per voxel, 4 when
+ * its slab schedule stores the work array slab by slab (zblock), plus edge buffers).  Returns
+ * MBS_EINVAL/MBS_EUNSUPPORTED for descriptors mbs_plan_create rejects. */
 mbs_status mbs_plan_bytes(const mbs_plan_desc* desc, size_t* device_bytes);
 
 /* Create a plan on the current HIP device; hip_stream is a hipStream_t (NULL = default

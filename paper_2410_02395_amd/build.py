@@ -28,6 +28,9 @@ COMMON = [
     "-std=c++17",
     # keep the compiler from emitting packed FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit fused multiply-adds: the kernels write every fma they use, so the rounding of
+    # a result does not depend on how the compiler schedules the code around it
+    "-ffp-contract=off",
     "-I", os.path.join(ROOT, "include"),
     "-I", CSRC,
     "-Wall",
@@ -60,6 +63,23 @@ def build_library(verbose: bool = False, out: str = LIB, defines=(), build_dir: 
     return out
 
 
+STREAM_CEILINGS = os.path.join(PKG, "stream_ceilings")
+
+
+def build_stream_ceilings(verbose: bool = False, out: str = STREAM_CEILINGS) -> str:
+    """Compile the stand-alone HBM streaming-rate program (``bench.py --stream-ceilings``)."""
+    cmd = [HIPCC, *[a for a in COMMON if a != "-fPIC"], "-x", "hip", os.path.join(CSRC, "stream_ceilings.hip"),
+           "-o", out + ".tmp"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed for stream_ceilings.hip:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    os.replace(out + ".tmp", out)
+    if verbose:
+        print(f"built {out}")
+    return out
+
+
 if __name__ == "__main__":
     build_library(verbose=True)
+    build_stream_ceilings(verbose=True)
     sys.exit(0)

@@ -54,13 +54,19 @@ struct Geo {
   int32_t reg_off[3][3]; // offsets of region d along each axis (axis d itself: slab code)
   int64_t face_vox;      // sum of reg_count (per subdomain)
   int32_t cus;           // compute units of the device (persistent grid size)
-  int32_t pad;
+  // layout of the work array W: z-line by z-line (wsh < 0), or in blocks of 2^wsh z values
+  // (the slab schedule of the strided passes), element (s, i0, i1, j) at
+  // s sub_vox + (j >> wsh) wplane + (i0 n1 + i1) 2^wsh + (j mod 2^wsh): one slab, one range
+  int32_t wsh;
+  int64_t wplane;        // n0 n1 2^wsh
 };
 
 // Per-slot pointers and scalars, in device memory (one table entry per slot).
 struct SlotDesc {
   float2* x;              // iterate, subdomain-major [S][n0][n1][n2]
   float2* W;              // work array (FFT in place)
+  float2* W2;             // output of the inverse y pass in z-lines where W is blocked (Geo::wsh
+                          // >= 0), read by the z pass; W itself otherwise
   float2* B;              // 1 - c (k^2 - k_b^2)
   float2* slab[3][4];     // per axis: 0 X (iterate edges), 1 U (edges of u), 2 Ex, 3 Eu
                           // each [S][2 sides][t][p][q]

@@ -54,6 +54,51 @@ __device__ __forceinline__ const T* cp(const T* p) {
 }
 #endif
 
+// Streaming loads and stores: with NT they carry the nontemporal hint (data that the kernel
+// touches once and that no later kernel of the iteration finds in a cache).
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef float f2v __attribute__((ext_vector_type(2)));
+template <bool NT, class P>
+__device__ __forceinline__ float2 ld_g(P p) {
+  if constexpr (NT) {
+    const f2v v = __builtin_nontemporal_load((const __attribute__((address_space(1))) f2v*)p);
+    return make_float2(v.x, v.y);
+  } else {
+    return *p;
+  }
+}
+template <bool NT, class P>
+__device__ __forceinline__ void st_g(P p, float2 v) {
+  if constexpr (NT) {
+    const f2v w = {v.x, v.y};
+    __builtin_nontemporal_store(w, (__attribute__((address_space(1))) f2v*)p);
+  } else {
+    *p = v;
+  }
+}
+#else
+template <bool NT, class P>
+__device__ __forceinline__ float2 ld_g(P p) { return *p; }
+template <bool NT, class P>
+__device__ __forceinline__ void st_g(P p, float2 v) { *p = v; }
+#endif
+// The z-line passes read and write each element once per iteration: their loads and stores
+// take the nontemporal hint (about 3 % faster on the fused z pass; MBS_LINE_NT=0 drops it).
+#ifndef MBS_LINE_NT
+#define MBS_LINE_NT 1
+#endif
+template <class P>
+__device__ __forceinline__ float2 ld_line(P p) { return ld_g<MBS_LINE_NT != 0>(p); }
+template <class P>
+__device__ __forceinline__ void st_line(P p, float2 v) { st_g<MBS_LINE_NT != 0>(p, v); }
+// The column passes: the x pass reads what the forward y pass wrote, and the inverse y pass what
+// the x pass wrote, from the memory-side cache when they run slab by slab, so those loads and
+// stores stay cached.  The inverse y pass's stores are read back only by the next z pass, after
+// the whole array has streamed: at 512-point columns they take the nontemporal hint (about 2 %
+// faster there; at 256 points the hint costs about 1 %).
+__host__ __device__ constexpr bool col_ld_nt(int) { return false; }
+__host__ __device__ constexpr bool col_st_nt(int kind, int n) { return kind == 1 && n >= 512; }
+
 // ---------------------------------------------------------------------------
 // complex helpers (float2 = interleaved re, im)
 // ---------------------------------------------------------------------------
@@ -63,7 +108,8 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   // explicit fma order: the same product rounds the same way in every kernel
   return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// |a|^2 in FP64 (the residual sums)
+__device__ __forceinline__ double norm2d(float2 a) { return fma((double)a.x, (double)a.x, (double)a.y * a.y); }
 // multiply by i*SIGN  (SIGN = -1: -i, SIGN = +1: +i)
 template <int SIGN>
 __device__ __forceinline__ float2 mul_si(float2 a) {
@@ -94,12 +140,11 @@ struct Bfly<SIGN, 3> {
   __device__ __forceinline__ static void run(float2* v) {
     const float h = 0.86602540378443864676f;  // sqrt(3)/2
     float2 s = cadd(v[1], v[2]);
-    float2 d = csub(v[1], v[2]);
-    float2 t = make_float2(v[0].x - 0.5f * s.x, v[0].y - 0.5f * s.y);
-    float2 r = mul_si<SIGN>(cscale(d, h));
+    float2 d = mul_si<SIGN>(csub(v[1], v[2]));
+    float2 t = make_float2(fmaf(-0.5f, s.x, v[0].x), fmaf(-0.5f, s.y, v[0].y));
     v[0] = cadd(v[0], s);
-    v[1] = cadd(t, r);
-    v[2] = csub(t, r);
+    v[1] = make_float2(fmaf(h, d.x, t.x), fmaf(h, d.y, t.y));
+    v[2] = make_float2(fmaf(-h, d.x, t.x), fmaf(-h, d.y, t.y));
   }
 };
 
@@ -117,6 +162,9 @@ struct Bfly<SIGN, 4> {
   }
 };
 
+// radix 8 as two radix-4 butterflies: the even outputs from a_m = v_m + v_{m+4}, the odd
+// ones from b_m = (v_m - v_{m+4}) w8^(SIGN m), w8 = exp(i pi/4).  w8^S b_1 and w8^3S b_3 enter
+// the odd radix-4 butterfly only as their sum and difference, each one rounding of an fma.
 template <int SIGN>
 struct Bfly<SIGN, 8> {
   __device__ __forceinline__ static void run(float2* v) {
@@ -127,20 +175,21 @@ struct Bfly<SIGN, 8> {
       a[m] = cadd(v[m], v[m + 4]);
       b[m] = csub(v[m], v[m + 4]);
     }
-    // b_m *= w8^(SIGN*m), w8 = exp(i pi/4)
-    {
-      float2 z = b[1];  // * (1 + SIGN i)/sqrt2
-      b[1] = SIGN > 0 ? make_float2(r * (z.x - z.y), r * (z.x + z.y))
-                      : make_float2(r * (z.x + z.y), r * (z.y - z.x));
-      b[2] = mul_si<SIGN>(b[2]);
-      z = b[3];  // * (-1 + SIGN i)/sqrt2
-      b[3] = SIGN > 0 ? make_float2(-r * (z.x + z.y), r * (z.x - z.y))
-                      : make_float2(r * (z.y - z.x), -r * (z.x + z.y));
-    }
     Bfly<SIGN, 4>::run(a);
-    Bfly<SIGN, 4>::run(b);
+    const float2 z1 = b[1], z3 = b[3];
+    // w8^S z1 = r u1, w8^3S z3 = r u3
+    const float2 u1 = SIGN > 0 ? make_float2(z1.x - z1.y, z1.x + z1.y) : make_float2(z1.x + z1.y, z1.y - z1.x);
+    const float2 u3 = SIGN > 0 ? make_float2(-(z3.x + z3.y), z3.x - z3.y) : make_float2(z3.y - z3.x, -(z3.x + z3.y));
+    const float2 p1 = make_float2(r * u1.x, r * u1.y);
+    const float2 s13 = make_float2(fmaf(r, u3.x, p1.x), fmaf(r, u3.y, p1.y));
+    const float2 d13 = mul_si<SIGN>(make_float2(fmaf(-r, u3.x, p1.x), fmaf(-r, u3.y, p1.y)));
+    const float2 b2 = mul_si<SIGN>(b[2]);
+    const float2 t0 = cadd(b[0], b2), t1 = csub(b[0], b2);
     v[0] = a[0]; v[2] = a[1]; v[4] = a[2]; v[6] = a[3];
-    v[1] = b[0]; v[3] = b[1]; v[5] = b[2]; v[7] = b[3];
+    v[1] = cadd(t0, s13);
+    v[5] = csub(t0, s13);
+    v[3] = cadd(t1, d13);
+    v[7] = csub(t1, d13);
   }
 };
 
@@ -194,15 +243,18 @@ __host__ __device__ constexpr int cols_per_tile_c(int n) {
 }
 
 // LINES whole lines of N contiguous elements; element (j, l) at l*N + j, padded by one
-// slot every 16 to spread the stride-R writes of the first stage over the banks.
+// slot every 2^MBS_LINE_PAD to spread the strided writes of the Stockham stages over the banks.
+#ifndef MBS_LINE_PAD
+#define MBS_LINE_PAD 4
+#endif
 template <int N, int LINES>
 struct LineTile {
   static constexpr int NT = kThreads;
   static constexpr int ELEMS = N * LINES;
-  static constexpr int LDS = ELEMS + ELEMS / 16 + 1;
+  static constexpr int LDS = ELEMS + (ELEMS >> MBS_LINE_PAD) + 1;
   __device__ __forceinline__ static int idx(int j, int l) {
     int f = l * N + j;
-    return f + (f >> 4);
+    return f + (f >> MBS_LINE_PAD);
   }
   template <int R>
   __device__ __forceinline__ static void bf(int b, int& i, int& l) {
@@ -417,6 +469,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // ---------------------------------------------------------------------------
 struct LineInfo {
   int64_t gbase;   // index of element 0 of the line in the subdomain-major arrays
+  int64_t wbase;   // the same in the layout of W (w_off)
   int64_t e0;      // slab offset for axis 0 (element j at e0 + j), -1 if not in a slab
   int64_t e1;      // slab offset for axis 1, -1 if not in a slab
   int64_t e2;      // slab offset for axis 2 at depth 0 of side 0 (-1: axis not corrected)
@@ -425,6 +478,21 @@ struct LineInfo {
   int32_t valid;
   int32_t on;      // the line's subdomain is iterated (subdomain activation, Sec. 3.1)
 };
+
+// W index of element 0 of the z-line (i0, i1) of subdomain s
+__device__ __forceinline__ int64_t w_line_base(int s, int i0, int i1, const Geo& g) {
+  const int64_t k = (int64_t)i0 * g.n[1] + i1;
+  return (int64_t)s * g.sub_vox + (g.wsh < 0 ? k * g.n[2] : k << g.wsh);
+}
+// offset of z index j from element 0 of its line (within one subdomain: below 2^31)
+__device__ __forceinline__ int32_t w_off(int j, const Geo& g) {
+  return g.wsh < 0 ? j : (j >> g.wsh) * (int32_t)g.wplane + (j & ((1 << g.wsh) - 1));
+}
+__device__ __forceinline__ int64_t w_at(int64_t wbase, int j, const Geo& g) { return wbase + w_off(j, g); }
+// Elements i + m S of a line with i < S (S = N/R: a thread's elements in a radix-R stage): W is
+// blocked only when n_2 and the block height are powers of two, so one of S and the block
+// height divides the other and w_off(i + m S) = w_off(i) + w_off(m S), a per-lane part and a
+// part that is the same for every lane.
 
 // subdomain s is iterated (all are when no activation mask is set)
 __device__ __forceinline__ bool sub_on(const uint32_t* act, int s) {
@@ -444,6 +512,7 @@ __device__ __forceinline__ void line_info(int64_t line, const Geo& g, const Slot
   const int s = (int)(r / n0);
   li.on = sub_on(sd.act, s) ? 1 : 0;
   li.gbase = line * n2;
+  li.wbase = w_line_base(s, i0, i1, g);
   li.e0 = -1;
   li.e1 = -1;
   li.e2 = -1;
@@ -544,8 +613,9 @@ __global__ __launch_bounds__(kThreads) void k_first(const SlotDesc* __restrict__
     int i, l;
     Tile::template bf<RL>(tid + q * kThreads, i, l);
     if (!info[l].valid) continue;
+    const auto p = W + (info[l].wbase + w_off(i, g));
 #pragma unroll
-    for (int m = 0; m < RL; ++m) W[info[l].gbase + i + m * (N / RL)] = o[q][m];
+    for (int m = 0; m < RL; ++m) st_line(p + w_off(m * (N / RL), g), o[q][m]);
   }
 }
 
@@ -572,7 +642,7 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
   __syncthreads();
   const auto X = gp(sd.x);
   const auto Bm = gp(sd.B);
-  const auto W = gp(sd.W);
+  const auto W2 = gp(sd.W2);  // output of the inverse y pass, in z-lines
   const auto U0 = gp(sd.slab[0][1]);
   const auto U1 = gp(sd.slab[1][1]);
   const auto U2 = gp(sd.slab[2][1]);
@@ -585,7 +655,7 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
     const LineInfo& li = info[ok ? l : 0];
 #pragma unroll
     for (int m = 0; m < R0; ++m)
-      v[q][m] = (ok && li.valid) ? W[li.gbase + i + m * (N / R0)] : make_float2(0.f, 0.f);
+      v[q][m] = (ok && li.valid) ? W2[li.gbase + i + m * (N / R0)] : make_float2(0.f, 0.f);
   }
   float2 o[PERL][RL];
   fft_tile<Tile, N, false, +1>(v, o, lds, tb.tw[2], tid);
@@ -607,7 +677,7 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
       const float2 xv = X[gi];
       const float2 u = csub(xv, o[q][m]);
       const float2 bu = cmul(Bm[gi], u);
-      X[gi] = make_float2(xv.x - alpha * bu.x, xv.y - alpha * bu.y);
+      X[gi] = make_float2(fmaf(-alpha, bu.x, xv.x), fmaf(-alpha, bu.y, xv.y));
       bool edge = false;
       if (li.e0 >= 0) { U0[li.e0 + j] = u; edge = true; }
       if (li.e1 >= 0) { U1[li.e1 + j] = u; edge = true; }
@@ -615,7 +685,7 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
         if (j < t) { U2[li.e2 + (int64_t)j * plane2] = u; edge = true; }
         else if (j >= N - t) { U2[li.e2 + (int64_t)(t + j - (N - t)) * plane2] = u; edge = true; }
       }
-      if (!edge) acc += (double)bu.x * bu.x + (double)bu.y * bu.y;
+      if (!edge) acc += norm2d(bu);
     }
   }
   const double s = block_sum(acc, red);
@@ -629,7 +699,7 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
 // before the LDS stages of the current one so that HBM traffic and LDS work overlap.
 // ---------------------------------------------------------------------------
 // elements [FROM, TO) of the flattened (butterfly q, input m) order; the default is all of them
-template <class Tile, int N, int R, int PER, bool FULL, int FROM = 0, int TO = PER * R, class Ptr>
+template <bool NT, class Tile, int N, int R, int PER, bool FULL, int FROM = 0, int TO = PER * R, class Ptr>
 __device__ __forceinline__ void load_cols(float2 (&v)[PER][R], Ptr tp, int stride, int ncols, int tid) {
   // tp: first element of the tile (uniform); per-lane offsets are 32-bit
 #pragma unroll
@@ -643,8 +713,8 @@ __device__ __forceinline__ void load_cols(float2 (&v)[PER][R], Ptr tp, int strid
     for (int m = 0; m < R; ++m) {
       if (q * R + m < FROM || q * R + m >= TO) continue;
       const int o = o0 + m * (N / R) * stride;
-      if (FULL) v[q][m] = tp[o];
-      else v[q][m] = in ? tp[o] : make_float2(0.f, 0.f);
+      if (FULL) v[q][m] = ld_g<NT>(tp + o);
+      else v[q][m] = in ? ld_g<NT>(tp + o) : make_float2(0.f, 0.f);
     }
   }
 }
@@ -652,7 +722,7 @@ __device__ __forceinline__ void load_cols(float2 (&v)[PER][R], Ptr tp, int strid
 // The persistent loop over this workgroup's tiles.  FULL: every tile has WC valid columns,
 // so loads and stores need no per-lane masks (no divergent branches inside the loop).
 template <int N, int KIND, bool FULL, class Ptr>
-__device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, int64_t tile, int64_t ntiles,
+__device__ __forceinline__ void col_loop(Ptr W, Ptr Wout, const Geo& g, const Tables& tb, int64_t tile, int64_t ntiles,
                                          float2* lds, const float2* s_tw, const float* s_p2x, const float* s_p2y,
                                          const float* s_p2z, float kb2, float cim, float inv,
                                          const int32_t* act_list, ColRange rg) {
@@ -665,7 +735,9 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
   const int CB = rg.ncb;  // column chunks walked: rg.cb0 .. rg.cb0 + rg.ncb - 1
   const int nfix = KIND == 2 ? n1 : n0;
-  const int stride = KIND == 2 ? n1 * n2 : n2;
+  // W in z-lines (wz = n2) or in blocks of wz z values (w_at)
+  const int wz = g.wsh < 0 ? n2 : (1 << g.wsh);
+  const int stride = KIND == 2 ? n1 * wz : wz;
   // tile t = (s * nfix + fix) * CB + cb, walked with a stride of gridDim.x without divisions
   int cb = (int)(tile % CB), fix = (int)((tile / CB) % nfix), sub = (int)(tile / ((int64_t)CB * nfix));
   const int gcb = (int)(gridDim.x % CB), grest = (int)(gridDim.x / CB);
@@ -674,13 +746,23 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
   // s_ of the list, read with a scalar load so no vector load besides the tiles is in flight
   auto tile_base = [&](int s_, int fix_, int cb_) -> int64_t {
     const int sid = act_list ? cp(act_list)[__builtin_amdgcn_readfirstlane(s_)] : rg.sub0 + s_;
-    return KIND == 2 ? ((int64_t)sid * N * n1 + fix_) * n2 + (rg.cb0 + cb_) * WC
-                     : (((int64_t)sid * n0 + fix_) * N) * n2 + (rg.cb0 + cb_) * WC;
+    const int z = (rg.cb0 + cb_) * WC;  // a tile never straddles two blocks of W
+    const int64_t blk = g.wsh < 0 ? 0 : (int64_t)(z >> g.wsh) * g.wplane;
+    const int zr = g.wsh < 0 ? z : (z & (wz - 1));
+    return (int64_t)sid * g.sub_vox + blk + (int64_t)fix_ * (KIND == 2 ? wz : n1 * wz) + zr;
+  };
+  // the inverse y pass over a blocked W writes z-lines to W2 (Wout), where the z pass reads them
+  const bool zl_out = KIND == 1 && g.wsh >= 0;
+  const int ostride = zl_out ? n2 : stride;
+  auto out_base = [&](int s_, int fix_, int cb_) -> int64_t {
+    if (!zl_out) return tile_base(s_, fix_, cb_);
+    const int sid = act_list ? cp(act_list)[__builtin_amdgcn_readfirstlane(s_)] : rg.sub0 + s_;
+    return ((int64_t)sid * n0 + fix_) * ((int64_t)n1 * n2) + (rg.cb0 + cb_) * WC;
   };
   int c0 = (rg.cb0 + cb) * WC, ncols = min(WC, n2 - c0);
   int64_t base = tile_base(sub, fix, cb);
   float2 cur[PER0][R0];
-  load_cols<Tile, N, R0, PER0, FULL>(cur, W + base, stride, ncols, tid);
+  load_cols<col_ld_nt(KIND), Tile, N, R0, PER0, FULL>(cur, W + base, stride, ncols, tid);
   fft_head<Tile, N, false, KIND == 1 ? +1 : -1, PER0, R0>(cur, lds, s_tw, tid);
   // output registers of the previous tile (the FFT result that is stored)
   constexpr int PERO = KIND == 2 ? PER0 : PERL;
@@ -708,14 +790,14 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
     constexpr int P1 = NSPL >= 2 ? Q4 + (E - Q4) / (NSPL - (Q4 ? 1 : 0)) : E;
     constexpr int P2 = NSPL >= 3 ? P1 + (E - P1) / 2 : E;
     const bool pf = MBS_COL_PREFETCH && more;
-    if (pf) load_cols<Tile, N, R0, PER0, FULL, 0, Q4 ? Q4 : P1>(nxt, W + nbase, stride, nncols, tid);
+    if (pf) load_cols<col_ld_nt(KIND), Tile, N, R0, PER0, FULL, 0, Q4 ? Q4 : P1>(nxt, W + nbase, stride, nncols, tid);
     keep_alive(o);
     if constexpr (KIND == 2) {
       float2 f[PERL][RL];
       constexpr int PL = plan_len(N);
       if constexpr (Q4 > 0 && PL > 1) {
         lds_stages<Tile, N, false, -1, 1, PL - 1>(lds, s_tw, tid);
-        if (pf) load_cols<Tile, N, R0, PER0, FULL, Q4, P1>(nxt, W + nbase, stride, nncols, tid);
+        if (pf) load_cols<col_ld_nt(KIND), Tile, N, R0, PER0, FULL, Q4, P1>(nxt, W + nbase, stride, nncols, tid);
         get_lds<Tile, N, RL, PERL>(lds, f, tid);
         bfly_regs<Tile, N, RL, plan_ns(N, PL - 1, false), -1, PERL>(f, s_tw, tid);
       } else {
@@ -733,40 +815,40 @@ __device__ __forceinline__ void col_loop(Ptr W, const Geo& g, const Tables& tb, 
         for (int m = 0; m < RL; ++m) {
           const float Pp = s_p2x[i + m * (N / RL)] + p21 + p2z;
           const float E = cim * (kb2 - Pp);
-          const float den = inv * __builtin_amdgcn_rcpf(1.f + E * E);  // 1 ulp reciprocal
+          const float den = inv * __builtin_amdgcn_rcpf(fmaf(E, E, 1.f));  // 1 ulp reciprocal
           f[q][m] = cmul(f[q][m], make_float2(den, -E * den));
         }
       }
-      if (P1 < P2 && pf) load_cols<Tile, N, R0, PER0, FULL, P1, P2>(nxt, W + nbase, stride, nncols, tid);
+      if (P1 < P2 && pf) load_cols<col_ld_nt(KIND), Tile, N, R0, PER0, FULL, P1, P2>(nxt, W + nbase, stride, nncols, tid);
       fft_head<Tile, N, true, +1, PERL, RL>(f, lds, s_tw, tid);
-      if (P2 < E && pf) load_cols<Tile, N, R0, PER0, FULL, P2, E>(nxt, W + nbase, stride, nncols, tid);
+      if (P2 < E && pf) load_cols<col_ld_nt(KIND), Tile, N, R0, PER0, FULL, P2, E>(nxt, W + nbase, stride, nncols, tid);
       fft_tail<Tile, N, true, +1, PERL, RL, PERO, RO>(f, o, lds, s_tw, tid);
     } else {
       constexpr int PL = plan_len(N);
       constexpr int SG = KIND == 1 ? +1 : -1;
       if constexpr (PL > 1 && NSPL >= 2) {
         lds_stages<Tile, N, false, SG, 1, PL - 1>(lds, s_tw, tid);
-        if (pf) load_cols<Tile, N, R0, PER0, FULL, P1, E>(nxt, W + nbase, stride, nncols, tid);
+        if (pf) load_cols<col_ld_nt(KIND), Tile, N, R0, PER0, FULL, P1, E>(nxt, W + nbase, stride, nncols, tid);
         get_lds<Tile, N, RL, PERL>(lds, o, tid);
         bfly_regs<Tile, N, RL, plan_ns(N, PL - 1, false), SG, PERL>(o, s_tw, tid);
       } else {
         fft_tail<Tile, N, false, SG, PER0, R0, PERL, RL>(cur, o, lds, s_tw, tid);
-        if (P1 < E && pf) load_cols<Tile, N, R0, PER0, FULL, P1, E>(nxt, W + nbase, stride, nncols, tid);
+        if (P1 < E && pf) load_cols<col_ld_nt(KIND), Tile, N, R0, PER0, FULL, P1, E>(nxt, W + nbase, stride, nncols, tid);
       }
     }
+    const auto tp = Wout + out_base(sub, fix, cb);
 #pragma unroll
     for (int q = 0; q < PERO; ++q) {
       if (!bvalid<Tile, RO>(q, tid)) continue;
       int i, c;
       Tile::template bf<RO>(tid + q * Tile::NT, i, c);
       if (!FULL && c >= ncols) continue;
-      const auto tp = W + base;
-      const int o0 = i * stride + c;
+      const int o0 = i * ostride + c;
 #pragma unroll
-      for (int m = 0; m < RO; ++m) tp[o0 + m * (N / RO) * stride] = o[q][m];
+      for (int m = 0; m < RO; ++m) st_g<col_st_nt(KIND, N)>(tp + o0 + m * (N / RO) * ostride, o[q][m]);
     }
     if (!more) break;
-    if (!MBS_COL_PREFETCH) load_cols<Tile, N, R0, PER0, FULL>(nxt, W + nbase, stride, nncols, tid);
+    if (!MBS_COL_PREFETCH) load_cols<col_ld_nt(KIND), Tile, N, R0, PER0, FULL>(nxt, W + nbase, stride, nncols, tid);
     fft_head<Tile, N, false, KIND == 1 ? +1 : -1, PER0, R0>(nxt, lds, s_tw, tid);
 #pragma unroll
     for (int q = 0; q < PER0; ++q)
@@ -825,11 +907,14 @@ __global__ __launch_bounds__(col_nt_c(N, KIND), col_wv_c(N, KIND)) void k_col(co
   }
   __syncthreads();
   const auto W = gp(sd.W);
+  const auto Wout = KIND == 1 ? gp(sd.W2) : W;
   const float kb2 = sd.kb2, cim = sd.c_im, inv = sd.inv_vox;
   if (n2 % WC == 0)
-    col_loop<N, KIND, true>(W, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv, act_list, rg);
+    col_loop<N, KIND, true>(W, Wout, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv, act_list,
+                            rg);
   else
-    col_loop<N, KIND, false>(W, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv, act_list, rg);
+    col_loop<N, KIND, false>(W, Wout, g, tb, tile, ntiles, lds, s_tw, s_p2x, s_p2y, s_p2z, kb2, cim, inv, act_list,
+                             rg);
 }
 
 
@@ -981,7 +1066,7 @@ __device__ __forceinline__ void load_lines(float2 (&v)[PER][R], Ptr a, const Lin
     const LineInfo& li = info[l];
     const int64_t base = (ok && li.valid && (!ON_ONLY || li.on)) ? li.gbase + i : i;
 #pragma unroll
-    for (int m = 0; m < R; ++m) v[q][m] = a[base + m * (N / R)];
+    for (int m = 0; m < R; ++m) v[q][m] = ld_line(a + base + m * (N / R));
   }
 }
 
@@ -1083,8 +1168,9 @@ __global__ __launch_bounds__(kThreads) void k_wpass(const SlotDesc* __restrict__
     int i, l;
     Tile::template bf<RL>(tid + q * Tile::NT, i, l);
     if (!info[l].valid || !info[l].on) continue;
+    const auto p = W + (info[l].wbase + w_off(i, g));
 #pragma unroll
-    for (int m = 0; m < RL; ++m) W[info[l].gbase + i + m * (N / RL)] = o[q][m];
+    for (int m = 0; m < RL; ++m) st_line(p + w_off(m * (N / RL), g), o[q][m]);
   }
 }
 
@@ -1121,9 +1207,10 @@ __global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__
   const float cim = sd.c_im, alpha = sd.alpha;
   const auto X = gp(sd.x);
   const auto W = gp(sd.W);
-  // every global read of the tile is issued here: v of iteration n, x_n and B
+  // every global read of the tile is issued here: v of iteration n (the inverse y pass's output,
+  // in z-lines), x_n and B
   float2 vin[PI][RI], xv[PER0][R0], bv[PER0][R0];
-  load_lines<Tile, N, RI, PI, true>(vin, W, info, tid);
+  load_lines<Tile, N, RI, PI, true>(vin, gp(sd.W2), info, tid);
   load_lines<Tile, N, R0, PER0, true>(xv, X, info, tid);
   load_lines<Tile, N, R0, PER0, true>(bv, gp(sd.B), info, tid);
   float2 u[PER0][R0];
@@ -1157,15 +1244,15 @@ __global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__
       const int64_t gi = li.gbase + j;
       float2 d = cmul(bv[q][m], u[q][m]);
       if (zc) d = cadd(d, z_edge_at<N, TM>(ez, l, j, t));
-      const float2 xn = make_float2(xv[q][m].x - alpha * d.x, xv[q][m].y - alpha * d.y);
-      X[gi] = xn;
+      const float2 xn = make_float2(fmaf(-alpha, d.x, xv[q][m].x), fmaf(-alpha, d.y, xv[q][m].y));
+      st_line(X + gi, xn);
       if (slab) {
         // x/y edge-slab line: its x/y corrections come later (k_slabA); keep the partial d in W
-        W[gi] = d;
+        st_line(W + (li.wbase + w_off(i, g) + w_off(m * (N / R0), g)), d);
         if (li.e0 >= 0) U0[li.e0 + j] = u[q][m];
         if (li.e1 >= 0) U1[li.e1 + j] = u[q][m];
       } else {
-        acc += (double)d.x * d.x + (double)d.y * d.y;
+        acc += norm2d(d);
       }
       xv[q][m] = xn;
     }
@@ -1212,8 +1299,9 @@ __global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__
       Tile::template bf<RL>(tid + q * Tile::NT, i, l);
       const LineInfo& li = info[l];
       if (!li.valid || !li.on || li.e0 >= 0 || li.e1 >= 0) continue;
+      const auto p = W + (li.wbase + w_off(i, g));
 #pragma unroll
-      for (int m = 0; m < RL; ++m) W[li.gbase + i + m * (N / RL)] = o[q][m];
+      for (int m = 0; m < RL; ++m) st_line(p + w_off(m * (N / RL), g), o[q][m]);
     }
   }
   const double ssum = block_sum(acc, red);
@@ -1238,7 +1326,8 @@ __global__ __launch_bounds__(kThreads) void k_slabA(const SlotDesc* __restrict__
     const int j = (int)(r - (int64_t)k * n2);
     int i0, i1;
     slab_line_coords(k, g, i0, i1);
-    const int64_t gi = (((int64_t)s * g.n[0] + i0) * g.n[1] + i1) * n2 + j;
+    const int64_t line = ((int64_t)s * g.n[0] + i0) * g.n[1] + i1;
+    const int64_t gi = line * n2 + j;
     float2 esum = make_float2(0.f, 0.f);
     int64_t a0 = -1, a1 = -1;
     if (g.a[0] && (i0 < t || i0 >= g.n[0] - t)) {
@@ -1251,13 +1340,13 @@ __global__ __launch_bounds__(kThreads) void k_slabA(const SlotDesc* __restrict__
       a1 = (((int64_t)s * 2 + side) * t + aa) * ((int64_t)g.n[0] * n2) + (int64_t)i0 * n2 + j;
       esum = cadd(esum, gp(sd.slab[1][3])[a1]);
     }
-    const float2 d = cadd(gp(sd.W)[gi], esum);
+    const float2 d = cadd(gp(sd.W)[w_at(w_line_base(s, i0, i1, g), j, g)], esum);
     const float2 xv = gp(sd.x)[gi];
-    const float2 xn = make_float2(xv.x - sd.alpha * esum.x, xv.y - sd.alpha * esum.y);
+    const float2 xn = make_float2(fmaf(-sd.alpha, esum.x, xv.x), fmaf(-sd.alpha, esum.y, xv.y));
     gp(sd.x)[gi] = xn;
     if (a0 >= 0) gp(sd.slab[0][0])[a0] = xn;
     if (a1 >= 0) gp(sd.slab[1][0])[a1] = xn;
-    acc = (double)d.x * d.x + (double)d.y * d.y;
+    acc = norm2d(d);
   }
   const double ssum = block_sum(acc, red);
   if (threadIdx.x == 0) gp(sd.part_face)[blockIdx.x] = ssum;
@@ -1288,7 +1377,7 @@ __global__ __launch_bounds__(kThreads) void k_xfer(const SlotDesc* __restrict__ 
       const auto E = gp(sd.slab[d][2]) + (int64_t)s * cnt;
       for (int64_t e = (int64_t)b * kThreads + threadIdx.x; e < cnt; e += step) {
         const float2 v = E[e];
-        acc += (double)v.x * v.x + (double)v.y * v.y;
+        acc += norm2d(v);
       }
     }
     const int P2 = g.P[2];
@@ -1318,7 +1407,7 @@ __global__ __launch_bounds__(kThreads) void k_xfer(const SlotDesc* __restrict__ 
               e.x = fmaf(C[a * T + j], h[j].x, e.x);
               e.y = fmaf(C[a * T + j], h[j].y, e.y);
             }
-            acc += c2 * ((double)e.x * e.x + (double)e.y * e.y);
+            acc += c2 * norm2d(e);
           }
         }
         if (hi_on) {  // first T values of the upper neighbour enter through the high edge
@@ -1333,7 +1422,7 @@ __global__ __launch_bounds__(kThreads) void k_xfer(const SlotDesc* __restrict__ 
               e.x = fmaf(C[j * T + a], l[j].x, e.x);
               e.y = fmaf(C[j * T + a], l[j].y, e.y);
             }
-            acc += c2 * ((double)e.x * e.x + (double)e.y * e.y);
+            acc += c2 * norm2d(e);
           }
         }
       }
@@ -1392,10 +1481,10 @@ __global__ __launch_bounds__(kThreads) void k_corr(const SlotDesc* __restrict__ 
     for (int b = 0; b < T; ++b) {
       const float cab = C[a * T + b];
       const float cba = C[b * T + a];
-      elo.x += cab * dh[b].x;
-      elo.y += cab * dh[b].y;
-      ehi.x += cba * dl[b].x;
-      ehi.y += cba * dl[b].y;
+      elo.x = fmaf(cab, dh[b].x, elo.x);
+      elo.y = fmaf(cab, dh[b].y, elo.y);
+      ehi.x = fmaf(cba, dl[b].x, ehi.x);
+      ehi.y = fmaf(cba, dl[b].y, ehi.y);
     }
     dst[(((int64_t)s * 2 + 0) * T + a) * plane + pq] = mul_negc(elo, cim);
     dst[(((int64_t)s * 2 + 1) * T + a) * plane + pq] = mul_negc(ehi, cim);
@@ -1455,12 +1544,12 @@ __global__ __launch_bounds__(kThreads) void k_face(const SlotDesc* __restrict__ 
     const float2 bu = cmul(gp(sd.B)[gi], u);
     const float2 dd = cadd(bu, esum);
     const float2 xv = gp(sd.x)[gi];
-    const float2 xn = make_float2(xv.x - sd.alpha * esum.x, xv.y - sd.alpha * esum.y);
+    const float2 xn = make_float2(fmaf(-sd.alpha, esum.x, xv.x), fmaf(-sd.alpha, esum.y, xv.y));
     gp(sd.x)[gi] = xn;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
       if (addr[k] >= 0) gp(sd.slab[k][0])[addr[k]] = xn;
-    acc = (double)dd.x * dd.x + (double)dd.y * dd.y;
+    acc = norm2d(dd);
   }
   const double ssum = block_sum(acc, red);
   if (threadIdx.x == 0) gp(sd.part_face)[blockIdx.x] = ssum;
@@ -1634,7 +1723,7 @@ __global__ __launch_bounds__(kThreads) void k_medium_B(const float2* __restrict_
     const double zr = re - kb2, zi = im;
     int g0, g1, g2;
     global_coords(v, g, g0, g1, g2);
-    B[local_index(g0, g1, g2, g)] = make_float2((float)(1.0 + c_im * zi), (float)(-c_im * zr));
+    B[local_index(g0, g1, g2, g)] = make_float2((float)fma(c_im, zi, 1.0), (float)(-c_im * zr));
   }
 }
 

@@ -80,6 +80,7 @@ double lap_kernel(int m) {
 struct Slot {
   float2* x = nullptr;
   float2* W = nullptr;
+  float2* W2 = nullptr;  // z-line output of the inverse y pass when W is blocked; else W
   float2* B = nullptr;
   float2* slab[3][4] = {};
   float2* ybox = nullptr;
@@ -209,8 +210,24 @@ int choose_zblock(const mbs_plan_desc* d, const Geo& g, bool fused) {
   return 0;
 }
 
+// With the slab schedule, W is stored in blocks of zblock z values when n_2 and zblock are powers
+// of two (zblock < n_2), so each slab of the strided passes is one contiguous range of memory;
+// otherwise in z-lines.  The arithmetic is the same either way.
+void set_w_layout(Geo& g, int zblock) {
+  g.wsh = -1;
+  g.wplane = 0;
+  const int n2 = g.n[2];
+  if (zblock <= 0 || zblock >= n2 || (zblock & (zblock - 1)) != 0 || (n2 & (n2 - 1)) != 0) return;
+  int sh = 0;
+  while ((1 << sh) < zblock) ++sh;
+  g.wsh = sh;
+  g.wplane = (int64_t)g.n[0] * g.n[1] * zblock;
+}
+
 mbs_status validate(const mbs_plan_desc* d, Geo* g) {
   if (!d) return MBS_EINVAL;
+  g->wsh = -1;  // W in z-lines unless the slab schedule blocks it (set_w_layout)
+  g->wplane = 0;
   if (d->max_batch < 1 || d->max_batch > 4096) return MBS_EINVAL;
   if (!(d->alpha > 0.0 && d->alpha <= 1.0)) return MBS_EINVAL;
   if (d->check_every < 0) return MBS_EINVAL;
@@ -293,7 +310,7 @@ size_t default_ybox(const Geo& g) {
 }
 
 size_t slot_bytes(const Geo& g) {
-  size_t b = 3 * (size_t)g.vox * sizeof(float2);
+  size_t b = (g.wsh >= 0 ? 4 : 3) * (size_t)g.vox * sizeof(float2);  // x, W, B (and W2)
   for (int d = 0; d < 3; ++d)
     if (g.a[d]) b += 4 * (size_t)slab_elems(g, d) * sizeof(float2);
   b += default_ybox(g) * sizeof(float2);
@@ -320,6 +337,7 @@ void fill_desc(mbs_plan p, int i) {
   SlotDesc& d = p->h_tab[i];
   d.x = s.x;
   d.W = s.W;
+  d.W2 = s.W2;
   d.B = s.B;
   for (int a = 0; a < 3; ++a)
     for (int k = 0; k < 4; ++k) d.slab[a][k] = s.slab[a][k];
@@ -909,6 +927,8 @@ mbs_status mbs_plan_bytes(const mbs_plan_desc* desc, size_t* device_bytes) {
   Geo g{};
   mbs_status st = validate(desc, &g);
   if (st != MBS_OK) return st;
+  // the layout of W the plan will choose (plan_create)
+  set_w_layout(g, choose_zblock(desc, g, !(desc->flags & MBS_NO_FUSION) && fusion_supported(g)));
   size_t b = (size_t)desc->max_batch * slot_bytes(g);
   b += (size_t)(desc->max_batch + 1) * (sizeof(SlotDesc) + sizeof(SlotState)) + sizeof(SlotDesc);
   for (int d = 0; d < 3; ++d) b += (size_t)g.n[d] * (sizeof(float2) + sizeof(float));
@@ -961,6 +981,7 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
   p->fused = !(desc->flags & MBS_NO_FUSION) && fusion_supported(g);
   p->activation = desc->activation;
   p->zblock = choose_zblock(desc, g, p->fused);
+  set_w_layout(p->geo, p->zblock);
   p->check_every = desc->check_every > 0 ? desc->check_every : 16;
   p->timing = (desc->flags & MBS_TIMING) != 0;
   p->use_graph = !(desc->flags & (MBS_NO_GRAPH | MBS_TIMING));
@@ -1024,6 +1045,8 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
     Slot& s = p->slots[i];
     if ((st = dalloc(p, &s.x, g.vox)) != MBS_OK) return fail(st);
     if ((st = dalloc(p, &s.W, g.vox)) != MBS_OK) return fail(st);
+    s.W2 = s.W;
+    if (p->geo.wsh >= 0 && (st = dalloc(p, &s.W2, g.vox)) != MBS_OK) return fail(st);
     if ((st = dalloc(p, &s.B, g.vox)) != MBS_OK) return fail(st);
     for (int d = 0; d < 3; ++d)
       if (g.a[d])
