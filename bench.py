@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {
     "workload": "dd1024",
     "fused": True,
-    "kernel_code_sha256": "5fdbb4df67bb1d9aedd380662fcedac40c1c19280424001b60fa6b5a24e6ec46",
-    "bytes": {"z_fwd": 2.137e9, "yxy_slabs": 51.55e9, "z_inv": 43.567e9, "edge_corr": 2.684e9,
-              "face": 3.158e9},
+    "kernel_code_sha256": "aece10757a9d8258dcf684b4f27bb5f14d725915c05111390ae3f56e6211078d",
+    "bytes": {"z_fwd": 2.133e9, "yxy_slabs": 51.588e9, "z_inv": 43.566e9, "edge_corr": 2.685e9,
+              "face": 3.147e9},
 }
 METRIC = "MBS voxel-updates/s + HBM GB/s at 1024³; served solves/s and p99 latency"
 
