@@ -83,7 +83,9 @@ typedef struct {
                          /* some transfer still exceeds the threshold.  Needs the fused z    */
                          /* pass and at most 4096 subdomains (else MBS_EUNSUPPORTED).        */
     int32_t zblock;      /* schedule of the three strided FFT passes (y, x with the Green    */
-                         /* multiply, inverse y): 0 = automatic, -1 = each pass over every   */
+                         /* multiply, inverse y): 0 = automatic (slabs when the work arrays  */
+                         /* exceed the memory-side cache; whole subdomains alternating over  */
+                         /* two streams when two fit in it), -1 = each pass over every       */
                          /* subdomain in turn, > 0 = the three passes subdomain by subdomain */
                          /* on slabs of zblock z values, so that a slab stays in the device's */
                          /* memory-side cache between them (must divide n_2 and be a         */

@@ -124,6 +124,7 @@ struct mbs_plan_s {
   hipStream_t stream = nullptr;   // caller's stream
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
   hipStream_t side_stream = nullptr; // second stream of the slab schedule (every other slab)
+  int slab_streams = 1;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int nslots = 0;
   bool corr = false;
@@ -188,25 +189,26 @@ bool valid_n(int n) { return n >= 8 && n <= 1024 && fft_size_supported(n); }
 
 // Memory-side cache (Infinity Cache) of the device, in bytes: 256 MB on MI355X.
 constexpr size_t kMallBytes = (size_t)256 << 20;
-// streams the slabs of the strided passes alternate over (2: each slab's working set is then
-// half the cache)
-#ifndef MBS_SLAB_STREAMS
-#define MBS_SLAB_STREAMS 1
-#endif
-
-// Slab height of the strided passes.  Automatic: when the work arrays of the plan exceed the
-// memory-side cache, the largest multiple of 16 dividing n_2 whose slab (n_0 n_1 z complex64
-// values of one subdomain) fits in it; otherwise every pass runs over every subdomain.
-int choose_zblock(const mbs_plan_desc* d, const Geo& g, bool fused) {
+// Slab height of the strided passes and the streams its slabs alternate over.  Automatic: when
+// the work arrays of the plan exceed the memory-side cache, whole subdomains on two streams if two
+// of them fit in the cache together (one subdomain's passes then overlap the start and the tail
+// of the other's); else the largest multiple of 16 dividing n_2 whose slab (n_0 n_1 z complex64
+// values of one subdomain) fits in it, on one stream; otherwise every pass runs over every
+// subdomain.  A given slab height runs on one stream.
+int choose_zblock(const mbs_plan_desc* d, const Geo& g, bool fused, int* streams = nullptr) {
+  if (streams) *streams = 1;
   if (!fused || d->zblock < 0) return 0;
   if (d->zblock > 0) return d->zblock;
   const size_t plane = (size_t)g.n[0] * g.n[1] * sizeof(float2);
   if ((size_t)g.S * g.sub_vox * sizeof(float2) * d->max_batch <= kMallBytes) return 0;
   const int wy = col_chunk_width(g.n[1], 0), wx = col_chunk_width(g.n[0], 2);
+  auto ok = [&](int z) { return g.n[2] % z == 0 && z % 16 == 0 && z % wy == 0 && z % wx == 0; };
+  if (ok(g.n[2]) && plane * g.n[2] * d->max_batch * 2 <= kMallBytes) {
+    if (streams) *streams = 2;
+    return g.n[2];
+  }
   for (int z = g.n[2]; z >= 16; --z)
-    if (g.n[2] % z == 0 && z % 16 == 0 && z % wy == 0 && z % wx == 0 &&
-        plane * z * d->max_batch * MBS_SLAB_STREAMS <= kMallBytes)
-      return z;
+    if (ok(z) && plane * z * d->max_batch <= kMallBytes) return z;
   return 0;
 }
 
@@ -980,7 +982,7 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
   p->corr01 = g.a[0] || g.a[1];
   p->fused = !(desc->flags & MBS_NO_FUSION) && fusion_supported(g);
   p->activation = desc->activation;
-  p->zblock = choose_zblock(desc, g, p->fused);
+  p->zblock = choose_zblock(desc, g, p->fused, &p->slab_streams);
   set_w_layout(p->geo, p->zblock);
   p->check_every = desc->check_every > 0 ? desc->check_every : 16;
   p->timing = (desc->flags & MBS_TIMING) != 0;
@@ -999,7 +1001,7 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
   }
   prepare_launches(p->geo);
   if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(MBS_EHIP);
-  if (p->zblock > 0 && MBS_SLAB_STREAMS > 1) {
+  if (p->zblock > 0 && p->slab_streams > 1) {
     if (hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking) != hipSuccess) return fail(MBS_EHIP);
     if (hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming) != hipSuccess) return fail(MBS_EHIP);
     if (hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming) != hipSuccess) return fail(MBS_EHIP);

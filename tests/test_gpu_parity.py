@@ -227,3 +227,34 @@ def test_slab_schedule_of_the_strided_passes_is_bitwise_neutral():
     for act in (0.0, 1e-2):
         assert np.array_equal(outs[(-1, act)], outs[(32, act)])
         assert np.array_equal(outs[(-1, act)], outs[(64, act)])
+
+
+def test_slab_schedules_chosen_automatically_are_bitwise_neutral():
+    """Where the work arrays exceed the memory-side cache the plan picks the slab schedule
+    itself: whole subdomains alternating over two streams when two fit in the cache
+    (512x512x256 as 2x2x2: 64 MiB subdomains), or slabs of 128 z values stored slab by slab
+    with the inverse y pass writing z-lines to a second array (512x512x1024 as 1x1x2: 1 GiB
+    subdomains, 512^2 cross-sections).  Either way every tile computes what the whole passes
+    compute."""
+    from paper_2410_02395_amd import mbs
+    from mbs_inputs import smoothed_random_medium
+    import torch
+    dev = torch.device("cuda:0")
+    k = 2 * math.pi / 4
+    for shape, split in (((512, 512, 256), (2, 2, 2)), ((512, 512, 1024), (1, 1, 2))):
+        print(f"shape {shape} split {split}", flush=True)
+        n = smoothed_random_medium(shape, 17, 1.0, 1.5, 2.0, device=dev)
+        S = torch.zeros(shape, dtype=torch.complex64, device=dev)
+        S[shape[0] // 3, shape[1] // 2, shape[2] // 2 + 5] = 1
+        outs = {}
+        for zb in (-1, 0):
+            for act in (0.0, 1e-2):
+                with mbs.Plan(shape, split, (0, 0, 0), 8, 1, 0.75, 0, 6, activation=act, zblock=zb) as plan:
+                    plan.set_medium(0, n, k, (8, 8, 8), 0.2)
+                    out, res = plan.solve(0, S, 0.0, 12)
+                    torch.cuda.synchronize()
+                    outs[(zb, act)] = out
+        for act in (0.0, 1e-2):
+            assert torch.equal(outs[(-1, act)], outs[(0, act)]), (shape, act)
+        del outs, n, S
+        torch.cuda.empty_cache()
