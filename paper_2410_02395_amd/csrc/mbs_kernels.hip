@@ -1174,17 +1174,8 @@ __global__ __launch_bounds__(kThreads) void k_wpass(const SlotDesc* __restrict__
   }
 }
 
-// waves per SIMD the fused z pass is compiled for (0: the compiler's choice)
-#ifndef MBS_FUSED_WAVES
-#define MBS_FUSED_WAVES 0
-#endif
-#if MBS_FUSED_WAVES > 0
-#define MBS_FUSED_ATTR __attribute__((amdgpu_waves_per_eu(MBS_FUSED_WAVES)))
-#else
-#define MBS_FUSED_ATTR
-#endif
 template <int N>
-__global__ __launch_bounds__(kThreads) MBS_FUSED_ATTR void k_fused(const SlotDesc* __restrict__ tab, Geo g, Tables tb) {
+__global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__ tab, Geo g, Tables tb) {
   const SlotDesc& sd = tab[blockIdx.y];
   if (sd.st->done != kRunning) return;
   constexpr int L = lines_per_wg_c(N);
