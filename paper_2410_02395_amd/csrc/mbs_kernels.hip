@@ -1314,30 +1314,32 @@ __global__ __launch_bounds__(kThreads) void k_slabA(const SlotDesc* __restrict__
   const SlotDesc& sd = tab[blockIdx.y];
   if (sd.st->done != kRunning) return;
   __shared__ double red[kThreads / 64];
-  const int per_col = slab_line_count(g);
+  // each subdomain has its own run of blocks: the subdomain follows from the block index, the
+  // line and z index from one 32-bit division (edge-slab voxels of one subdomain: below 2^31)
   const int n2 = g.n[2], t = g.t;
-  const int64_t per_sub = (int64_t)per_col * n2;
-  const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int per_sub = slab_line_count(g) * n2;
+  const int bps = (per_sub + kThreads - 1) / kThreads;
+  const int s = (int)blockIdx.x / bps;
+  const int r = ((int)blockIdx.x - s * bps) * kThreads + (int)threadIdx.x;
   double acc = 0.0;
-  const int s = (int)(gid / (per_sub > 0 ? per_sub : 1));
-  if (gid < (int64_t)g.S * per_sub && sub_on(sd.act, s)) {
-    const int64_t r = gid - (int64_t)s * per_sub;
-    const int k = (int)(r / n2);
-    const int j = (int)(r - (int64_t)k * n2);
+  if (r < per_sub && sub_on(sd.act, s)) {
+    const int k = r / n2;
+    const int j = r - k * n2;
     int i0, i1;
     slab_line_coords(k, g, i0, i1);
     const int64_t line = ((int64_t)s * g.n[0] + i0) * g.n[1] + i1;
     const int64_t gi = line * n2 + j;
     float2 esum = make_float2(0.f, 0.f);
-    int64_t a0 = -1, a1 = -1;
+    // edge-slab buffers of one axis hold S 2 t n_p n_q <= S n0 n1 n2 < 2^31 values
+    int a0 = -1, a1 = -1;
     if (g.a[0] && (i0 < t || i0 >= g.n[0] - t)) {
       const int side = i0 < t ? 0 : 1, aa = side ? i0 - (g.n[0] - t) : i0;
-      a0 = (((int64_t)s * 2 + side) * t + aa) * ((int64_t)g.n[1] * n2) + (int64_t)i1 * n2 + j;
+      a0 = ((s * 2 + side) * t + aa) * (g.n[1] * n2) + i1 * n2 + j;
       esum = cadd(esum, gp(sd.slab[0][3])[a0]);
     }
     if (g.a[1] && (i1 < t || i1 >= g.n[1] - t)) {
       const int side = i1 < t ? 0 : 1, aa = side ? i1 - (g.n[1] - t) : i1;
-      a1 = (((int64_t)s * 2 + side) * t + aa) * ((int64_t)g.n[0] * n2) + (int64_t)i0 * n2 + j;
+      a1 = ((s * 2 + side) * t + aa) * (g.n[0] * n2) + i0 * n2 + j;
       esum = cadd(esum, gp(sd.slab[1][3])[a1]);
     }
     const float2 d = cadd(gp(sd.W)[w_at(w_line_base(s, i0, i1, g), j, g)], esum);
@@ -2059,7 +2061,7 @@ int host_slab_line_count(const Geo& g) {
 bool fusion_supported(const Geo& g) { return lines_per_wg_c(g.n[2]) % g.P[2] == 0; }
 
 int64_t slabA_blocks(const Geo& g) {
-  return ((int64_t)g.S * host_slab_line_count(g) * g.n[2] + kThreads - 1) / kThreads;
+  return (int64_t)g.S * (((int64_t)host_slab_line_count(g) * g.n[2] + kThreads - 1) / kThreads);
 }
 
 hipError_t launch_fused(const SlotDesc* tab, int nslots, const Geo& g, const Tables& tb, hipStream_t s) {

@@ -316,7 +316,7 @@ size_t slot_bytes(const Geo& g) {
   for (int d = 0; d < 3; ++d)
     if (g.a[d]) b += 4 * (size_t)slab_elems(g, d) * sizeof(float2);
   b += default_ybox(g) * sizeof(float2);
-  b += (size_t)(last_pass_blocks(g) + face_blocks(g) + 1) * sizeof(double);
+  b += (size_t)(last_pass_blocks(g) + std::max(face_blocks(g), slabA_blocks(g)) + 1) * sizeof(double);
   b += (size_t)(kHistCap + kReduceBlocks) * sizeof(double);
   return b;
 }
@@ -989,6 +989,7 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
   p->use_graph = !(desc->flags & (MBS_NO_GRAPH | MBS_TIMING));
   p->n_main = last_pass_blocks(g);
   p->n_face = face_blocks(g);
+  const int64_t n_part_face = std::max(p->n_face, slabA_blocks(g));  // face or edge-slab partials
   auto fail = [&](mbs_status s) {
     mbs_plan_destroy(p);
     return s;
@@ -1057,7 +1058,7 @@ mbs_status mbs_plan_create(const mbs_plan_desc* desc, void* hip_stream, mbs_plan
     s.ybox_cap = default_ybox(g);
     if ((st = dalloc(p, &s.ybox, s.ybox_cap)) != MBS_OK) return fail(st);
     if ((st = dalloc(p, &s.part_main, p->n_main)) != MBS_OK) return fail(st);
-    if ((st = dalloc(p, &s.part_face, p->n_face)) != MBS_OK) return fail(st);
+    if ((st = dalloc(p, &s.part_face, n_part_face)) != MBS_OK) return fail(st);
     if ((st = dalloc(p, &s.hist, kHistCap)) != MBS_OK) return fail(st);
     if ((st = dalloc(p, &s.part_red, kReduceBlocks)) != MBS_OK) return fail(st);
     if (hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming) != hipSuccess) return fail(MBS_EHIP);
