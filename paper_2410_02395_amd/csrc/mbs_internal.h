@@ -64,7 +64,7 @@ struct Geo {
 // Per-slot pointers and scalars, in device memory (one table entry per slot).
 struct SlotDesc {
   float2* x;              // iterate, subdomain-major [S][n0][n1][n2]
-  float2* W;              // work array (FFT in place)
+  float2* W;              // work array (FFTs in place; layout Geo::wsh)
   float2* W2;             // output of the inverse y pass in z-lines where W is blocked (Geo::wsh
                           // >= 0), read by the z pass; W itself otherwise
   float2* B;              // 1 - c (k^2 - k_b^2)

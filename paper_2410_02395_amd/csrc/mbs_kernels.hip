@@ -4,7 +4,7 @@
 // One iteration of Eq. 6 on every subdomain of every active slot (default sequence):
 //   k_col<.,0>  FFT along y of w                           (Eq. 5)
 //   k_col<.,2>  FFT along x, multiply by the (L+I)^-1 symbol, inverse FFT along x
-//   k_col<.,1>  inverse FFT along y
+//   k_col<.,1>  inverse FFT along y (into W2, in z-lines, where W is stored slab by slab)
 //               (the three column passes run whole, or subdomain by subdomain on z slabs
 //               that stay in the memory-side cache between them)
 //   k_fused     per global z-line: inverse FFT along z, u = x - v, d = B u + z-edge terms,

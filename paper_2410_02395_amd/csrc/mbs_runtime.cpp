@@ -2,8 +2,10 @@
 //
 // A plan owns, per slot (independent solve): the iterate x, the work array W
 // and the diagonal B = 1 - c (k^2 - k_b^2) of (I - V), all subdomain-major
-// ([S][n0][n1][n2], z contiguous), four t-deep edge-slab buffers per corrected
-// axis, the source on its bounding box and the FP64 residual partials.  The
+// ([S][n0][n1][n2], z contiguous; W stored slab by slab, with a z-line copy W2 of
+// the inverse y pass's output, when the strided passes run on slabs), four
+// t-deep edge-slab buffers per corrected axis, the source on its bounding box and
+// the FP64 residual partials.  The
 // FP64 scalars of Eq. 9 (k_b^2, ||k^2 - k_b^2||_inf, ||A12||, c) live on the
 // host.  Iterations are enqueued as hipGraphs of `check_every` iterations over
 // all slots; a slot whose device stop flag is set skips every kernel.  Between
