@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {
     "workload": "dd1024",
     "fused": True,
-    "kernel_code_sha256": "a8daafce129bae456c0c5f1b90d1015ae8bf6409e253f9cb05dc32d80398d2e8",
-    "bytes": {"z_fwd": 2.134e9, "yxy_slabs": 51.587e9, "z_inv": 43.566e9, "edge_corr": 2.685e9,
-              "face": 3.145e9},
+    "kernel_code_sha256": "81d70142dc977a583388be6d8e2a78b06992e1ea8d4f281b8bf3c4d753945c5a",
+    "bytes": {"z_fwd": 2.134e9, "yxy_slabs": 51.575e9, "z_inv": 43.566e9, "edge_corr": 2.685e9,
+              "face": 3.146e9},
 }
 METRIC = "MBS voxel-updates/s + HBM GB/s at 1024³; served solves/s and p99 latency"
 
