@@ -32,8 +32,8 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {
     "workload": "dd1024",
     "fused": True,
-    "kernel_code_sha256": "81d70142dc977a583388be6d8e2a78b06992e1ea8d4f281b8bf3c4d753945c5a",
-    "bytes": {"z_fwd": 2.134e9, "yxy_slabs": 51.575e9, "z_inv": 43.566e9, "edge_corr": 2.685e9,
+    "kernel_code_sha256": "c52f648eb18b3a304156cc1dc1246b16dfc69515359d78f683cd5502ac6378c2",
+    "bytes": {"z_fwd": 2.134e9, "yxy_slabs": 51.577e9, "z_inv": 43.566e9, "edge_corr": 2.685e9,
               "face": 3.146e9},
 }
 METRIC = "MBS voxel-updates/s + HBM GB/s at 1024³; served solves/s and p99 latency"
