@@ -141,6 +141,45 @@ def test_resume_from_checkpoint_is_bitwise():
     assert np.array_equal(rest, full)
 
 
+def test_async_solve_reports_progress_and_matches_the_blocking_solve():
+    """mbs_solve_async + mbs_poll: while the slot runs, poll returns MBS_EBUSY with the iterations
+    and residual of its last completed launch (non-decreasing iterations, at most the final count);
+    the finished field is bitwise the blocking solve's."""
+    import time
+    import torch
+    from paper_2410_02395_amd import mbs
+    shape, split, periodic = (64, 64, 128), (2, 2, 2), (0, 0, 0)
+    n, S = random_case(shape, seed=9)
+    k = 2 * math.pi / 4
+    dev = torch.device("cuda:0")
+    nt = torch.from_numpy(np.ascontiguousarray(n, np.complex64)).to(dev)
+    St = torch.from_numpy(np.ascontiguousarray(S, np.complex64)).to(dev)
+    iters = 400
+    with mbs.Plan(shape, split, periodic, 8, 1, 0.75, 0, 10) as plan:
+        plan.set_medium(0, nt, k, (4, 4, 4), 0.2)
+        ref, rref = plan.solve(0, St, 0.0, iters)
+        ref = ref.cpu().numpy()
+        out = torch.empty(shape, dtype=torch.complex64, device=dev)
+        plan.solve_async(0, St, 0.0, iters, out)
+        seen = []
+        t0 = time.perf_counter()
+        while True:
+            res = plan.poll(0)
+            if res is not None:
+                break
+            seen.append(plan.progress[0])
+            assert time.perf_counter() - t0 < 60.0
+            time.sleep(0.0005)
+        torch.cuda.synchronize()
+    its = [it for it, _ in seen]
+    print(f"{len(seen)} busy polls, iterations seen {its[:3]} ... {its[-3:]}", flush=True)
+    assert res["iterations"] == rref["iterations"] == iters
+    assert all(a <= b for a, b in zip(its, its[1:]))
+    assert all(0 <= it <= iters for it in its)
+    assert all(e >= 0.0 for it, e in seen if it > 0)
+    assert np.array_equal(out.cpu().numpy(), ref)
+
+
 def test_graph_and_eager_launches_agree_bitwise():
     from paper_2410_02395_amd import mbs
     shape, split, periodic = (32, 32, 32), (2, 2, 1), (0, 0, 1)
