@@ -87,7 +87,13 @@ struct SlotDesc {
   double* xfer;           // [S][kXferBlocks] partial sums of the field transferred into
                           // inactive subdomains (nullptr: activation off)
   int32_t n_act;          // entries of act_list
-  int32_t pad;
+  // B of a lossless medium (Im n = 0 everywhere): only Im B is stored, one float per voxel, and
+  // Re B = 1 + c_im k0^2 ramp(r) follows from the absorbing layers (bx_k = c_im k0^2; the ramp
+  // of axis d rises by rstep[d] per voxel over the outer rw[d] voxels of each side)
+  int32_t b_ramp;
+  float bx_k;
+  float rstep[3];
+  int32_t rw[3];
 };
 
 // Part of a column pass: subdomains [sub0, sub0 + nsub) and z column chunks [cb0, cb0 + ncb) of
@@ -137,6 +143,7 @@ int64_t face_blocks(const Geo& g);
 struct MediumStats {
   double re_min, re_max, im_min;
   double nonfinite;
+  double nim_max;  // max |Im n| (0: a lossless medium)
 };
 hipError_t launch_medium_stats(const float2* n, const Geo& g, double k0sq, const int32_t* width,
                                double ramp_max, MediumStats* partials, int64_t nblocks,
@@ -145,7 +152,7 @@ hipError_t launch_medium_kmax(const float2* n, const Geo& g, double k0sq, const 
                               double ramp_max, double kb2, double* partials, int64_t nblocks,
                               hipStream_t s);
 hipError_t launch_medium_B(const float2* n, const Geo& g, double k0sq, const int32_t* width,
-                           double ramp_max, double kb2, double c_im, float2* B, hipStream_t s);
+                           double ramp_max, double kb2, double c_im, float2* B, int compact, hipStream_t s);
 int64_t setup_blocks(const Geo& g);
 hipError_t launch_source_bbox(const float2* S, const Geo& g, int32_t* bbox /*lo3,hi3,nonfinite*/,
                               hipStream_t s);

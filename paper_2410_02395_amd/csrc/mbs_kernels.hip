@@ -76,7 +76,14 @@ __device__ __forceinline__ void st_g(P p, float2 v) {
     *p = v;
   }
 }
+template <bool NT, class P>
+__device__ __forceinline__ float ld_gf(P p) {
+  if constexpr (NT) return __builtin_nontemporal_load((const __attribute__((address_space(1))) float*)p);
+  else return *p;
+}
 #else
+template <bool NT, class P>
+__device__ __forceinline__ float ld_gf(P p) { return *p; }
 template <bool NT, class P>
 __device__ __forceinline__ float2 ld_g(P p) { return *p; }
 template <bool NT, class P>
@@ -491,6 +498,8 @@ struct LineInfo {
   int32_t jlo, jhi;
   int32_t valid;
   int32_t on;      // the line's subdomain is iterated (subdomain activation, Sec. 3.1)
+  float r01;       // absorbing ramp of the line's x and y position (compact B)
+  int32_t gz0;     // global z of element 0
 };
 
 // W index of element 0 of the z-line (i0, i1) of subdomain s
@@ -508,6 +517,26 @@ __device__ __forceinline__ int64_t w_at(int64_t wbase, int j, const Geo& g) { re
 // height divides the other and w_off(i + m S) = w_off(i) + w_off(m S), a per-lane part and a
 // part that is the same for every lane.
 
+// Absorbing ramp of global index i along axis d, as the medium set-up applies it (Sec. 4: the
+// outer rw[d] voxels of each side, rising linearly to the boundary)
+__device__ __forceinline__ float ramp_axis(const SlotDesc& sd, const Geo& g, int d, int i) {
+  const int W = sd.rw[d];
+  float r = 0.f;
+  if (i < W) r = sd.rstep[d] * (float)(W - i);
+  if (i >= g.N[d] - W) r = fmaxf(r, sd.rstep[d] * (float)(i - (g.N[d] - W) + 1));
+  return r;
+}
+
+// B = 1 - c (k^2 - k_b^2) at element j (index gi) of a line: stored whole, or for a lossless
+// medium Im B stored and Re B = 1 + c_im k0^2 ramp(r) from the line's position
+__device__ __forceinline__ float2 b_line(const SlotDesc& sd, const Geo& g, const LineInfo& li, int j, int64_t gi) {
+  if (sd.b_ramp) {
+    const float r = fmaxf(li.r01, ramp_axis(sd, g, 2, li.gz0 + j));
+    return make_float2(fmaf(sd.bx_k, r, 1.f), gp(reinterpret_cast<const float*>(sd.B))[gi]);
+  }
+  return gp(sd.B)[gi];
+}
+
 // subdomain s is iterated (all are when no activation mask is set)
 __device__ __forceinline__ bool sub_on(const uint32_t* act, int s) {
   return act == nullptr || ((act[s >> 5] >> (s & 31)) & 1u) != 0u;
@@ -519,11 +548,18 @@ __device__ __forceinline__ void line_info(int64_t line, const Geo& g, const Slot
   const int64_t nlines = (int64_t)g.S * n0 * n1;
   li.valid = line < nlines;
   li.on = 0;
+  li.r01 = 0.f;
+  li.gz0 = 0;
   if (!li.valid) return;
   const int i1 = (int)(line % n1);
   const int64_t r = line / n1;
   const int i0 = (int)(r % n0);
   const int s = (int)(r / n0);
+  {
+    const int c2 = s % g.P[2], c1 = (s / g.P[2]) % g.P[1], c0 = s / (g.P[2] * g.P[1]);
+    li.r01 = fmaxf(ramp_axis(sd, g, 0, c0 * n0 + i0), ramp_axis(sd, g, 1, c1 * n1 + i1));
+    li.gz0 = c2 * n2;
+  }
   li.on = sub_on(sd.act, s) ? 1 : 0;
   li.gbase = line * n2;
   li.wbase = w_line_base(s, i0, i1, g);
@@ -588,7 +624,6 @@ __global__ __launch_bounds__(kThreads) void k_first(const SlotDesc* __restrict__
   const int t = g.t;
   const int64_t plane2 = (int64_t)g.n[0] * g.n[1];
   const auto X = gp(sd.x);
-  const auto Bm = gp(sd.B);
   const auto E0 = gp(sd.slab[0][2]);
   const auto E1 = gp(sd.slab[1][2]);
   const auto E2 = gp(sd.slab[2][2]);
@@ -607,7 +642,7 @@ __global__ __launch_bounds__(kThreads) void k_first(const SlotDesc* __restrict__
       float2 w = make_float2(0.f, 0.f);
       if (ok && li.valid) {
         const int64_t gi = li.gbase + j;
-        w = cmul(Bm[gi], X[gi]);
+        w = cmul(b_line(sd, g, li, j, gi), X[gi]);
         if (li.e0 >= 0) w = cadd(w, E0[li.e0 + j]);
         if (li.e1 >= 0) w = cadd(w, E1[li.e1 + j]);
         if (li.e2 >= 0) {
@@ -655,7 +690,6 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
   for (int l = tid; l < L; l += kThreads) line_info(line0 + l, g, sd, info[l]);
   __syncthreads();
   const auto X = gp(sd.x);
-  const auto Bm = gp(sd.B);
   const auto W2 = gp(sd.W2);  // output of the inverse y pass, in z-lines
   const auto U0 = gp(sd.slab[0][1]);
   const auto U1 = gp(sd.slab[1][1]);
@@ -690,7 +724,7 @@ __global__ __launch_bounds__(kThreads) void k_last(const SlotDesc* __restrict__ 
       const int64_t gi = li.gbase + j;
       const float2 xv = X[gi];
       const float2 u = csub(xv, o[q][m]);
-      const float2 bu = cmul(Bm[gi], u);
+      const float2 bu = cmul(b_line(sd, g, li, j, gi), u);
       X[gi] = make_float2(fmaf(-alpha, bu.x, xv.x), fmaf(-alpha, bu.y, xv.y));
       bool edge = false;
       if (li.e0 >= 0) { U0[li.e0 + j] = u; edge = true; }
@@ -1084,6 +1118,34 @@ __device__ __forceinline__ void load_lines(float2 (&v)[PER][R], Ptr a, const Lin
   }
 }
 
+// B on this thread's elements (load_lines' element order and clamping): for a lossless medium
+// one float per element (Im B) is read and Re B follows from the absorbing ramp
+template <class Tile, int N, int R, int PER, bool ON_ONLY>
+__device__ __forceinline__ void load_b_lines(float2 (&v)[PER][R], const SlotDesc& sd, const Geo& g,
+                                             const LineInfo* info, int tid) {
+  if (!sd.b_ramp) {
+    load_lines<Tile, N, R, PER, ON_ONLY>(v, gp(sd.B), info, tid);
+    return;
+  }
+  const auto Bi = gp(reinterpret_cast<const float*>(sd.B));
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    int i = 0, l = 0;
+    const bool ok = bvalid<Tile, R>(q, tid);
+    if (ok) Tile::template bf<R>(tid + q * Tile::NT, i, l);
+    const LineInfo& li = info[l];
+    const int64_t base = (ok && li.valid && (!ON_ONLY || li.on)) ? li.gbase + i : i;
+    float im[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) im[m] = ld_gf<MBS_LINE_NT != 0>(Bi + base + m * (N / R));
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const float r = fmaxf(li.r01, ramp_axis(sd, g, 2, li.gz0 + i + m * (N / R)));
+      v[q][m] = make_float2(fmaf(sd.bx_k, r, 1.f), im[m]);
+    }
+  }
+}
+
 // z edge values of this thread's elements to LDS (first t to zlo, last t to zhi); with ON_ONLY
 // a line whose subdomain is not iterated has the edge values of its field, zero
 template <class Tile, int N, int R, int PER, int TM, bool ON_ONLY>
@@ -1145,7 +1207,7 @@ __global__ __launch_bounds__(kThreads) void k_wpass(const SlotDesc* __restrict__
   // or lines of newly activated subdomains) reads all of them: x is zero where not iterated
   float2 xv[PER0][R0], bv[PER0][R0];
   load_lines<Tile, N, R0, PER0, SLAB_ONLY>(xv, gp(sd.x), info, tid);
-  load_lines<Tile, N, R0, PER0, SLAB_ONLY>(bv, gp(sd.B), info, tid);
+  load_b_lines<Tile, N, R0, PER0, SLAB_ONLY>(bv, sd, g, info, tid);
   if (zc) {
     put_z_edges<Tile, N, R0, PER0, TM, SLAB_ONLY>(xv, zlo, zhi, info, t, tid);
     __syncthreads();
@@ -1226,7 +1288,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__
   float2 vin[PI][RI], xv[PER0][R0], bv[PER0][R0];
   load_lines<Tile, N, RI, PI, true>(vin, gp(sd.W2), info, tid);
   load_lines<Tile, N, R0, PER0, true>(xv, X, info, tid);
-  load_lines<Tile, N, R0, PER0, true>(bv, gp(sd.B), info, tid);
+  load_b_lines<Tile, N, R0, PER0, true>(bv, sd, g, info, tid);
   float2 u[PER0][R0];
   fft_tile<Tile, N, true, +1>(vin, u, lds, s_tw, tid);
   // u = x - v; the z edge terms of u
@@ -1557,7 +1619,16 @@ __global__ __launch_bounds__(kThreads) void k_face(const SlotDesc* __restrict__ 
       u = gp(sd.slab[k][1])[ad];
     }
     const int64_t gi = (((int64_t)s * g.n[0] + i[0]) * g.n[1] + i[1]) * g.n[2] + i[2];
-    const float2 bu = cmul(gp(sd.B)[gi], u);
+    float2 bv;
+    if (sd.b_ramp) {
+      const int c2 = s % g.P[2], c1 = (s / g.P[2]) % g.P[1], c0 = s / (g.P[2] * g.P[1]);
+      const float rr = fmaxf(fmaxf(ramp_axis(sd, g, 0, c0 * g.n[0] + i[0]), ramp_axis(sd, g, 1, c1 * g.n[1] + i[1])),
+                             ramp_axis(sd, g, 2, c2 * g.n[2] + i[2]));
+      bv = make_float2(fmaf(sd.bx_k, rr, 1.f), gp(reinterpret_cast<const float*>(sd.B))[gi]);
+    } else {
+      bv = gp(sd.B)[gi];
+    }
+    const float2 bu = cmul(bv, u);
     const float2 dd = cadd(bu, esum);
     const float2 xv = gp(sd.x)[gi];
     const float2 xn = make_float2(fmaf(-sd.alpha, esum.x, xv.x), fmaf(-sd.alpha, esum.y, xv.y));
@@ -1672,8 +1743,8 @@ __device__ __forceinline__ void wavenumber_sq(const float2* n, int64_t v, const 
 __global__ __launch_bounds__(kThreads) void k_medium_stats(const float2* __restrict__ n, Geo g,
                                                            double k0sq, Int3 w, double rmax,
                                                            MediumStats* part) {
-  __shared__ double smin[kThreads], smax[kThreads], simin[kThreads], snf[kThreads];
-  double mn = INFINITY, mx = -INFINITY, imn = INFINITY, nf = 0.0;
+  __shared__ double smin[kThreads], smax[kThreads], simin[kThreads], snf[kThreads], snim[kThreads];
+  double mn = INFINITY, mx = -INFINITY, imn = INFINITY, nf = 0.0, nim = 0.0;
   for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < g.vox;
        v += (int64_t)gridDim.x * kThreads) {
     double re, im;
@@ -1683,11 +1754,13 @@ __global__ __launch_bounds__(kThreads) void k_medium_stats(const float2* __restr
     mn = fmin(mn, re);
     mx = fmax(mx, re);
     imn = fmin(imn, im);
+    nim = fmax(nim, fabs((double)n[v].y));
   }
   smin[threadIdx.x] = mn;
   smax[threadIdx.x] = mx;
   simin[threadIdx.x] = imn;
   snf[threadIdx.x] = nf;
+  snim[threadIdx.x] = nim;
   __syncthreads();
   for (int off = kThreads / 2; off > 0; off >>= 1) {
     if (threadIdx.x < off) {
@@ -1695,6 +1768,7 @@ __global__ __launch_bounds__(kThreads) void k_medium_stats(const float2* __restr
       smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + off]);
       simin[threadIdx.x] = fmin(simin[threadIdx.x], simin[threadIdx.x + off]);
       snf[threadIdx.x] += snf[threadIdx.x + off];
+      snim[threadIdx.x] = fmax(snim[threadIdx.x], snim[threadIdx.x + off]);
     }
     __syncthreads();
   }
@@ -1703,6 +1777,7 @@ __global__ __launch_bounds__(kThreads) void k_medium_stats(const float2* __restr
     part[blockIdx.x].re_max = smax[0];
     part[blockIdx.x].im_min = simin[0];
     part[blockIdx.x].nonfinite = snf[0];
+    part[blockIdx.x].nim_max = snim[0];
   }
 }
 
@@ -1730,7 +1805,7 @@ __global__ __launch_bounds__(kThreads) void k_medium_kmax(const float2* __restri
 // B = 1 - c (k^2 - k_b^2), c = i c_im, written subdomain-major
 __global__ __launch_bounds__(kThreads) void k_medium_B(const float2* __restrict__ n, Geo g, double k0sq,
                                                        Int3 w, double rmax, double kb2, double c_im,
-                                                       float2* __restrict__ B) {
+                                                       float2* __restrict__ B, int compact) {
   for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < g.vox;
        v += (int64_t)gridDim.x * kThreads) {
     double re, im;
@@ -1739,7 +1814,10 @@ __global__ __launch_bounds__(kThreads) void k_medium_B(const float2* __restrict_
     const double zr = re - kb2, zi = im;
     int g0, g1, g2;
     global_coords(v, g, g0, g1, g2);
-    B[local_index(g0, g1, g2, g)] = make_float2((float)fma(c_im, zi, 1.0), (float)(-c_im * zr));
+    if (compact)  // lossless medium: Im B only (Re B = 1 + c_im k0^2 ramp is rebuilt where it is used)
+      reinterpret_cast<float*>(B)[local_index(g0, g1, g2, g)] = (float)(-c_im * zr);
+    else
+      B[local_index(g0, g1, g2, g)] = make_float2((float)fma(c_im, zi, 1.0), (float)(-c_im * zr));
   }
 }
 
@@ -2168,10 +2246,10 @@ hipError_t launch_medium_kmax(const float2* n, const Geo& g, double k0sq, const 
 }
 
 hipError_t launch_medium_B(const float2* n, const Geo& g, double k0sq, const int32_t* width,
-                           double ramp_max, double kb2, double c_im, float2* B, hipStream_t s) {
+                           double ramp_max, double kb2, double c_im, float2* B, int compact, hipStream_t s) {
   Int3 w{{width[0], width[1], width[2]}};
   hipLaunchKernelGGL(k_medium_B, dim3(grid_1d(g.vox)), dim3(kThreads), 0, s, n, g, k0sq, w, ramp_max,
-                     kb2, c_im, B);
+                     kb2, c_im, B, compact);
   return hipGetLastError();
 }
 

@@ -99,6 +99,9 @@ struct Slot {
   hipEvent_t done_ev = nullptr;
   void* field_out = nullptr;
   double kb2 = 0, c_im = 0, K = 0;
+  bool b_ramp = false;  // lossless medium: B holds Im B only (SlotDesc::b_ramp)
+  double k0sq = 0, ramp_max = 0;
+  int32_t ramp_w[3] = {0, 0, 0};
   double rho_ref = 0;
   int32_t last_status = MBS_OK;
   int64_t start_seq = 0;   // chunks launched before this solve started
@@ -364,7 +367,12 @@ void fill_desc(mbs_plan p, int i) {
   d.act_list = act ? s.list_d : nullptr;
   d.n_act = act ? s.n_act : p->geo.S;
   d.xfer = act ? p->d_xfer + (size_t)i * p->geo.S * kXferBlocks : nullptr;
-  d.pad = 0;
+  d.b_ramp = s.b_ramp ? 1 : 0;
+  d.bx_k = (float)(s.c_im * s.k0sq);
+  for (int k = 0; k < 3; ++k) {
+    d.rw[k] = s.ramp_w[k];
+    d.rstep[k] = s.ramp_w[k] > 0 ? (float)(s.ramp_max / (double)s.ramp_w[k]) : 0.f;
+  }
 }
 
 mbs_status push_desc(mbs_plan p, int i) {
@@ -1128,12 +1136,13 @@ mbs_status mbs_set_medium(mbs_plan p, int32_t slot, const void* n_dev, double k0
   HIP_TRY(hipMemcpyAsync(p->h_stats.data(), p->d_stats, p->setup_nb * sizeof(MediumStats),
                          hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
-  double re_min = INFINITY, re_max = -INFINITY, im_min = INFINITY, nf = 0;
+  double re_min = INFINITY, re_max = -INFINITY, im_min = INFINITY, nf = 0, nim_max = 0;
   for (const auto& m : p->h_stats) {
     re_min = std::min(re_min, m.re_min);
     re_max = std::max(re_max, m.re_max);
     im_min = std::min(im_min, m.im_min);
     nf += m.nonfinite;
+    nim_max = std::max(nim_max, m.nim_max);
   }
   s.has_medium = false;
   if (nf > 0) return MBS_ENONFINITE;
@@ -1149,7 +1158,17 @@ mbs_status mbs_set_medium(mbs_plan p, int32_t slot, const void* n_dev, double k0
   const double denom = K + (double)(g.a[0] + g.a[1] + g.a[2]) * p->normC;
   if (!(denom > 0.0)) return MBS_EDEGENERATE;
   const double c_im = -0.95 / denom;
-  HIP_TRY(launch_medium_B(n, g, k0sq, width, rmax, kb2, c_im, s.B, p->stream));
+  // a lossless medium (Im n = 0): Im k^2 is the absorbing ramp alone, so Re B = 1 + c_im k0^2 ramp
+  // is a function of position and only Im B is stored
+#ifndef MBS_COMPACT_B
+#define MBS_COMPACT_B 1
+#endif
+  const bool compact = MBS_COMPACT_B && nim_max == 0.0;
+  HIP_TRY(launch_medium_B(n, g, k0sq, width, rmax, kb2, c_im, s.B, compact ? 1 : 0, p->stream));
+  s.b_ramp = compact;
+  s.k0sq = k0sq;
+  s.ramp_max = rmax;
+  for (int k = 0; k < 3; ++k) s.ramp_w[k] = width[k];
   s.kb2 = kb2;
   s.K = K;
   s.c_im = c_im;

@@ -94,6 +94,19 @@ def test_decomposed_fixed_iterations(shape, split, periodic, t):
 @pytest.mark.parametrize("shape,split,periodic,t", [
     ((64, 64, 64), (2, 2, 2), (0, 0, 0), 8),
     ((48, 24, 96), (2, 1, 2), (1, 0, 0), 4),
+])
+def test_lossy_medium_fixed_iterations(shape, split, periodic, t):
+    """A medium with Im n > 0 keeps the whole of B in memory; a lossless one (every other case
+    here) stores Im B only and rebuilds Re B = 1 + c_im k0^2 ramp from the absorbing layers."""
+    n, S = random_case(shape, seed=19)
+    n = (n + 0.01j).astype(np.complex64)
+    k = 2 * math.pi / 4
+    _compare(shape, split, periodic, t, n, S, k, (4, 4, 4), 0.2, 60)
+
+
+@pytest.mark.parametrize("shape,split,periodic,t", [
+    ((64, 64, 64), (2, 2, 2), (0, 0, 0), 8),
+    ((48, 24, 96), (2, 1, 2), (1, 0, 0), 4),
     ((16, 24, 144), (1, 1, 3), (1, 1, 1), 4),    # three segments on a cyclic z axis
     ((16, 16, 2048), (1, 1, 2), (0, 0, 0), 8),   # two 1024-point segments per workgroup
 ])
