@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {
     "workload": "dd1024",
     "fused": True,
-    "kernel_code_sha256": "c52f648eb18b3a304156cc1dc1246b16dfc69515359d78f683cd5502ac6378c2",
-    "bytes": {"z_fwd": 2.134e9, "yxy_slabs": 51.577e9, "z_inv": 43.566e9, "edge_corr": 2.685e9,
-              "face": 3.146e9},
+    "kernel_code_sha256": "dc84852283c10b029086a4366e1a1ee75853a5360db6d2d11a980d0c71457523",
+    "bytes": {"z_fwd": 1.868e9, "yxy_slabs": 51.576e9, "z_inv": 39.271e9, "edge_corr": 2.685e9,
+              "face": 3.092e9},
 }
 METRIC = "MBS voxel-updates/s + HBM GB/s at 1024³; served solves/s and p99 latency"
 
