@@ -193,6 +193,43 @@ def test_async_solve_reports_progress_and_matches_the_blocking_solve():
     assert np.array_equal(out.cpu().numpy(), ref)
 
 
+def test_slots_with_lossless_and_lossy_media_batch_bitwise():
+    """Two slots of one plan iterate in the same launches, one with a lossless medium (Im B stored
+    alone) and one with a lossy medium (the whole of B): each field is bitwise the field of the same
+    slot solved alone."""
+    import torch
+    from paper_2410_02395_amd import mbs
+    shape, split, periodic = (64, 32, 64), (2, 1, 2), (0, 0, 0)
+    n0, S = random_case(shape, seed=31)
+    n1 = (n0 + 0.02j).astype(np.complex64)
+    k = 2 * math.pi / 4
+    dev = torch.device("cuda:0")
+    media = [torch.from_numpy(np.ascontiguousarray(m, np.complex64)).to(dev) for m in (n0, n1)]
+    St = torch.from_numpy(np.ascontiguousarray(S, np.complex64)).to(dev)
+    iters = 37
+    alone = []
+    with mbs.Plan(shape, split, periodic, 8, 2, 0.75, 0, 8) as plan:
+        for slot in range(2):
+            plan.set_medium(slot, media[slot], k, (4, 4, 4), 0.2)
+        for slot in range(2):
+            out, res = plan.solve(slot, St, 0.0, iters)
+            assert res["iterations"] == iters
+            alone.append(out.cpu().numpy())
+        outs = [torch.empty(shape, dtype=torch.complex64, device=dev) for _ in range(2)]
+        for slot in range(2):
+            plan.solve_async(slot, St, 0.0, iters, outs[slot])
+        done = [None, None]
+        while any(d is None for d in done):
+            for slot in range(2):
+                if done[slot] is None:
+                    done[slot] = plan.poll(slot)
+        torch.cuda.synchronize()
+    assert all(d["iterations"] == iters for d in done)
+    assert not np.array_equal(alone[0], alone[1])
+    for slot in range(2):
+        assert np.array_equal(outs[slot].cpu().numpy(), alone[slot]), slot
+
+
 def test_graph_and_eager_launches_agree_bitwise():
     from paper_2410_02395_amd import mbs
     shape, split, periodic = (32, 32, 32), (2, 2, 1), (0, 0, 1)
