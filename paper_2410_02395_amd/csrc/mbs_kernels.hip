@@ -1128,6 +1128,10 @@ __device__ __forceinline__ void load_b_lines(float2 (&v)[PER][R], const SlotDesc
     return;
   }
   const auto Bi = gp(reinterpret_cast<const float*>(sd.B));
+  // a z ramp no wider than N/R reaches only the first and last element of a butterfly: the
+  // others (i + m N/R, 0 < m < R-1) are at least N/R from both ends of their segment, and a
+  // segment starts at a multiple of N
+  const bool narrow = sd.rw[2] <= N / R;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     int i = 0, l = 0;
@@ -1135,15 +1139,29 @@ __device__ __forceinline__ void load_b_lines(float2 (&v)[PER][R], const SlotDesc
     if (ok) Tile::template bf<R>(tid + q * Tile::NT, i, l);
     const LineInfo& li = info[l];
     const int64_t base = (ok && li.valid && (!ON_ONLY || li.on)) ? li.gbase + i : i;
-    float im[R];
 #pragma unroll
-    for (int m = 0; m < R; ++m) im[m] = ld_gf<MBS_LINE_NT != 0>(Bi + base + m * (N / R));
+    for (int m = 0; m < R; ++m) v[q][m].y = ld_gf<MBS_LINE_NT != 0>(Bi + base + m * (N / R));
+    if (narrow) {
+      const float rb = fmaf(sd.bx_k, li.r01, 1.f);
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-      const float r = fmaxf(li.r01, ramp_axis(sd, g, 2, li.gz0 + i + m * (N / R)));
-      v[q][m] = make_float2(fmaf(sd.bx_k, r, 1.f), im[m]);
+      for (int m = 0; m < R; ++m) {
+        v[q][m].x = rb;
+        if (m == 0 || m == R - 1)
+          v[q][m].x = fmaf(sd.bx_k, fmaxf(li.r01, ramp_axis(sd, g, 2, li.gz0 + i + m * (N / R))), 1.f);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < R; ++m)
+        v[q][m].x = fmaf(sd.bx_k, fmaxf(li.r01, ramp_axis(sd, g, 2, li.gz0 + i + m * (N / R))), 1.f);
     }
   }
+}
+
+// t <= kMaxT: where kMaxT <= N/R only the first (m = 0) and last (m = R-1) element of a
+// butterfly (i + m N/R) can lie within t of either end of its segment
+template <int N, int R>
+__device__ __forceinline__ bool z_edge_possible(int m) {
+  return kMaxT > N / R || m == 0 || m == R - 1;
 }
 
 // z edge values of this thread's elements to LDS (first t to zlo, last t to zhi); with ON_ONLY
@@ -1160,6 +1178,7 @@ __device__ __forceinline__ void put_z_edges(const float2 (&v)[PER][R], float2 (*
     const bool zero = ON_ONLY && !info[l].on;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
+      if (!z_edge_possible<N, R>(m)) continue;
       const int j = i + m * (N / R);
       const float2 e = zero ? make_float2(0.f, 0.f) : v[q][m];
       if (j < t) zlo[l][j] = e;
@@ -1230,7 +1249,7 @@ __global__ __launch_bounds__(kThreads) void k_wpass(const SlotDesc* __restrict__
         if (j >= li.jlo && j < li.jhi) e = Y[li.ybase + j];
         if (li.e0 >= 0) e = cadd(e, E0[li.e0 + j]);
         if (li.e1 >= 0) e = cadd(e, E1[li.e1 + j]);
-        if (zc) e = cadd(e, z_edge_at<N, TM>(ez, l, j, t));
+        if (zc && z_edge_possible<N, R0>(m)) e = cadd(e, z_edge_at<N, TM>(ez, l, j, t));
         w = form_w(bv[q][m], xv[q][m], e);
       }
       v[q][m] = w;
@@ -1251,7 +1270,7 @@ __global__ __launch_bounds__(kThreads) void k_wpass(const SlotDesc* __restrict__
 }
 
 template <int N>
-__global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__ tab, Geo g, Tables tb) {
+__global__ __launch_bounds__(kThreads, 4) void k_fused(const SlotDesc* __restrict__ tab, Geo g, Tables tb) {
   const SlotDesc& sd = tab[blockIdx.y];
   if (sd.st->done != kRunning) return;
   constexpr int L = lines_per_wg_c(N);
@@ -1319,7 +1338,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__
       const int j = i + m * (N / R0);
       const int64_t gi = li.gbase + j;
       float2 d = cmul(bv[q][m], u[q][m]);
-      if (zc) d = cadd(d, z_edge_at<N, TM>(ez, l, j, t));
+      if (zc && z_edge_possible<N, R0>(m)) d = cadd(d, z_edge_at<N, TM>(ez, l, j, t));
       const float2 xn = make_float2(fmaf(-alpha, d.x, xv[q][m].x), fmaf(-alpha, d.y, xv[q][m].y));
       st_line(X + gi, xn);
       if (slab) {
@@ -1360,7 +1379,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const SlotDesc* __restrict__
         if (plain) {
           float2 e = make_float2(0.f, 0.f);
           if (j >= li.jlo && j < li.jhi) e = Y[li.ybase + j];
-          if (zc) e = cadd(e, z_edge_at<N, TM>(ez, l, j, t));
+          if (zc && z_edge_possible<N, R0>(m)) e = cadd(e, z_edge_at<N, TM>(ez, l, j, t));
           w = form_w(bv[q][m], xv[q][m], e);
         }
         v[q][m] = w;
