@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {
     "workload": "dd1024",
     "fused": True,
-    "kernel_code_sha256": "dc84852283c10b029086a4366e1a1ee75853a5360db6d2d11a980d0c71457523",
-    "bytes": {"z_fwd": 1.868e9, "yxy_slabs": 51.576e9, "z_inv": 39.271e9, "edge_corr": 2.685e9,
-              "face": 3.092e9},
+    "kernel_code_sha256": "f173a94caa19822e85f38b98cb1ee687098b189243fa8eb2e618e3c11f21e5b6",
+    "bytes": {"z_fwd": 1.869e9, "yxy_slabs": 51.576e9, "z_inv": 39.272e9, "edge_corr": 2.685e9,
+              "face": 3.100e9},
 }
 METRIC = "MBS voxel-updates/s + HBM GB/s at 1024³; served solves/s and p99 latency"
 

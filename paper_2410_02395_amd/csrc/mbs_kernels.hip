@@ -551,10 +551,19 @@ __device__ __forceinline__ void line_info(int64_t line, const Geo& g, const Slot
   li.r01 = 0.f;
   li.gz0 = 0;
   if (!li.valid) return;
-  const int i1 = (int)(line % n1);
-  const int64_t r = line / n1;
-  const int i0 = (int)(r % n0);
-  const int s = (int)(r / n0);
+  int i0, i1, s;
+  if (nlines <= (int64_t)UINT32_MAX) {
+    // 32-bit division where the line index fits: a fraction of the 64-bit sequence
+    const uint32_t u = (uint32_t)line, r = u / (uint32_t)n1;
+    i1 = (int)(u - r * (uint32_t)n1);
+    s = (int)(r / (uint32_t)n0);
+    i0 = (int)(r - (uint32_t)s * (uint32_t)n0);
+  } else {
+    const int64_t r = line / n1;
+    i1 = (int)(line - r * n1);
+    s = (int)(r / n0);
+    i0 = (int)(r - (int64_t)s * n0);
+  }
   {
     const int c2 = s % g.P[2], c1 = (s / g.P[2]) % g.P[1], c0 = s / (g.P[2] * g.P[1]);
     li.r01 = fmaxf(ramp_axis(sd, g, 0, c0 * n0 + i0), ramp_axis(sd, g, 1, c1 * n1 + i1));
@@ -1039,7 +1048,7 @@ __device__ __forceinline__ void global_lines(const Geo& g, const SlotDesc& sd, L
       info[l].valid = 0;
       continue;
     }
-    const int col = (int)(G / per_col);
+    const int col = nG <= (int64_t)UINT32_MAX ? (int)((uint32_t)G / (uint32_t)per_col) : (int)(G / per_col);
     const int k = (int)(G - (int64_t)col * per_col);
     int i0, i1;
     if (SLAB_ONLY) slab_line_coords(k, g, i0, i1);
