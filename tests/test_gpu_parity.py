@@ -124,6 +124,17 @@ def test_separate_and_fused_z_passes_agree(shape, split, periodic, t):
     assert d <= 1e-5
 
 
+@pytest.mark.parametrize("rw_z", [64, 80])
+def test_z_ramp_at_and_beyond_the_butterfly_stride(rw_z):
+    """Two 512-point z segments (first radix 8, so a thread's elements are 64 apart) of a
+    lossless medium, whose Re B the fused z pass rebuilds from the ramp: a 64-voxel z ramp
+    reaches only the first and last element of each butterfly, an 80-voxel one reaches
+    further in and takes the per-element path; both against the oracle."""
+    shape = (16, 16, 1024)
+    n, S = random_case(shape, seed=23)
+    _compare(shape, (1, 1, 2), (0, 0, 0), 8, n, S, 2 * math.pi / 4, (4, 4, rw_z), 0.2, 40)
+
+
 @pytest.mark.parametrize("shape", [(8, 8, 8), (16, 12, 24), (96, 32, 64), (12, 192, 8), (256, 8, 32), (384, 16, 32),
                                    (512, 8, 16), (768, 8, 16), (1024, 8, 16), (8, 768, 16), (8, 1024, 16),
                                    (16, 8, 768), (16, 8, 1024)])
